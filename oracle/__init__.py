@@ -1,0 +1,215 @@
+"""FP64 CPU oracle for finite element assembly -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this package.  It wraps ``fem_oracle.c`` (plain C, FP64) through ctypes and shares
+nothing with the HIP library.  What each routine computes, and which passage of the
+paper it follows, is stated in ``fem_oracle.c``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "fem_oracle.c")
+LIB = os.path.join(_HERE, "libfem_oracle.so")
+
+LOAD = {"none": 0, "const": 1, "sinprod": 2}
+
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle with the host C compiler (plain -O2, no fast-math)."""
+    tmp = LIB + ".tmp"
+    subprocess.check_call(
+        ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", SRC, "-o", tmp, "-lm"]
+    )
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        i32 = ctypes.c_int
+        dbl = ctypes.c_double
+        L.fo_simplex_monomial.argtypes = [i32, P]
+        L.fo_simplex_monomial.restype = dbl
+        L.fo_quad_rule.argtypes = [i32, i32, P, P]
+        L.fo_quad_rule.restype = i32
+        L.fo_pattern.argtypes = [i32, i32, i64, i64, P, P, P]
+        L.fo_pattern.restype = i64
+        L.fo_signed_volumes.argtypes = [i32, i64, i64, P, P, P]
+        L.fo_element_p1.argtypes = [i32, P, dbl, dbl, P]
+        L.fo_assemble_p1.argtypes = [i32, i64, i64, P, P, P, dbl, i32, P, P, P, P, P, P, P]
+        L.fo_backward_p1.argtypes = [i32, i64, i64, P, P, P, dbl, i32, P, P, P, P, P, P, P, P, P]
+        L.fo_element_p2_elasticity.argtypes = [P, dbl, dbl, P]
+        L.fo_p2_phi_mean.argtypes = [P]
+        L.fo_assemble_p2_elasticity.argtypes = [i64, i64, P, P, P, P, i32, P, P, P, P, P, P, P]
+        L.fo_backward_p2_elasticity.argtypes = [
+            i64, i64, P, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, P
+        ]
+        for name in ("fo_signed_volumes", "fo_element_p1", "fo_p2_phi_mean",
+                     "fo_assemble_p1", "fo_backward_p1", "fo_element_p2_elasticity",
+                     "fo_assemble_p2_elasticity", "fo_backward_p2_elasticity"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def simplex_monomial(d: int, alpha) -> float:
+    a = np.zeros(4, dtype=np.int32)
+    a[: len(alpha)] = alpha
+    return lib().fo_simplex_monomial(d, _p(a))
+
+
+def quad_rule(d: int, degree: int):
+    """(bary [n][d+1], weights [n]) with weights summing to 1."""
+    bary = np.zeros(14 * 4)
+    w = np.zeros(14)
+    n = lib().fo_quad_rule(d, degree, _p(bary), _p(w))
+    if n < 0:
+        raise ValueError("no such rule")
+    return bary[: n * (d + 1)].reshape(n, d + 1), w[:n]
+
+
+def pattern(npe: int, ncomp: int, n_nodes: int, conn):
+    conn = _i32(conn)
+    E = conn.shape[1]
+    rowptr = np.zeros(n_nodes * ncomp + 1, dtype=np.int64)
+    nnz = lib().fo_pattern(npe, ncomp, n_nodes, E, _p(conn), _p(rowptr), None)
+    if nnz < 0:
+        raise RuntimeError(f"oracle pattern failed ({nnz})")
+    colind = np.zeros(nnz, dtype=np.int32)
+    nnz2 = lib().fo_pattern(npe, ncomp, n_nodes, E, _p(conn), _p(rowptr), _p(colind))
+    assert nnz2 == nnz
+    return rowptr, colind
+
+
+def signed_volumes(mesh) -> np.ndarray:
+    coords = _f64(mesh.coords)
+    conn = _i32(mesh.conn)
+    out = np.zeros(conn.shape[1])
+    _check(lib().fo_signed_volumes(mesh.dim, coords.shape[1], conn.shape[1], _p(coords),
+                                   _p(conn), _p(out)), "signed_volumes")
+    return out
+
+
+def element_p1(xv, kappa=1.0, c=0.0):
+    """xv: [(d+1)][d] vertex coordinates -> A [(d+1)][(d+1)] (no load)."""
+    xv = _f64(xv)
+    d = xv.shape[1]
+    A = np.zeros((d + 1) * (d + 1))
+    _check(lib().fo_element_p1(d, _p(xv), kappa, c, _p(A)), "element_p1")
+    return A.reshape(d + 1, d + 1)
+
+
+def element_p2_elasticity(xv, lam, mu):
+    xv = _f64(xv)
+    K = np.zeros(900)
+    _check(lib().fo_element_p2_elasticity(_p(xv), lam, mu, _p(K)), "element_p2")
+    return K.reshape(30, 30)
+
+
+def p2_phi_mean():
+    out = np.zeros(10)
+    _check(lib().fo_p2_phi_mean(_p(out)), "p2_phi_mean")
+    return out
+
+
+def assemble_p1(mesh, kappa, c, load, load_const, rowptr, colind):
+    """Returns (values, rhs, abs_values, abs_rhs)."""
+    coords = _f64(mesh.coords)
+    conn = _i32(mesh.conn)
+    kappa = _f64(kappa).ravel()
+    N, E = coords.shape[1], conn.shape[1]
+    nnz = int(rowptr[-1])
+    vals, avals = np.zeros(nnz), np.zeros(nnz)
+    rhs, arhs = np.zeros(N), np.zeros(N)
+    lc = _f64(np.atleast_1d(load_const if load_const is not None else [0.0]))
+    _check(lib().fo_assemble_p1(mesh.dim, N, E, _p(coords), _p(conn), _p(kappa), float(c),
+                                LOAD[load], _p(lc), _p(rowptr), _p(colind), _p(vals), _p(rhs),
+                                _p(avals), _p(arhs)), "assemble_p1")
+    return vals, rhs, avals, arhs
+
+
+def backward_p1(mesh, kappa, c, load, load_const, rowptr, colind, Gbar, gbar, want_coords=True):
+    """Returns (dkappa, abs_dkappa, dcoords [d][N], abs_dcoords [d][N])."""
+    coords = _f64(mesh.coords)
+    conn = _i32(mesh.conn)
+    kappa = _f64(kappa).ravel()
+    N, E, d = coords.shape[1], conn.shape[1], mesh.dim
+    dk, adk = np.zeros(E), np.zeros(E)
+    dx = np.zeros((d, N)) if want_coords else None
+    adx = np.zeros((d, N)) if want_coords else None
+    lc = _f64(np.atleast_1d(load_const if load_const is not None else [0.0]))
+    Gbar = None if Gbar is None else _f64(Gbar)
+    gbar = None if gbar is None else _f64(gbar)
+    _check(lib().fo_backward_p1(d, N, E, _p(coords), _p(conn), _p(kappa), float(c), LOAD[load],
+                                _p(lc), _p(rowptr), _p(colind), _p(Gbar), _p(gbar), _p(dk),
+                                _p(adk), _p(dx), _p(adx)), "backward_p1")
+    return dk, adk, dx, adx
+
+
+def assemble_p2_elasticity(mesh, lam, mu, load, body_force, rowptr, colind):
+    coords = _f64(mesh.coords)
+    conn = _i32(mesh.conn)
+    lam = _f64(lam)
+    mu = _f64(mu)
+    N, E = coords.shape[1], conn.shape[1]
+    nnz = int(rowptr[-1])
+    vals, avals = np.zeros(nnz), np.zeros(nnz)
+    rhs, arhs = np.zeros(3 * N), np.zeros(3 * N)
+    bf = _f64(body_force if body_force is not None else [0.0, 0.0, 0.0])
+    _check(lib().fo_assemble_p2_elasticity(N, E, _p(coords), _p(conn), _p(lam), _p(mu),
+                                           LOAD[load], _p(bf), _p(rowptr), _p(colind), _p(vals),
+                                           _p(rhs), _p(avals), _p(arhs)), "assemble_p2")
+    return vals, rhs, avals, arhs
+
+
+def backward_p2_elasticity(mesh, lam, mu, load, body_force, rowptr, colind, Gbar, gbar,
+                           want_coords=True):
+    """Returns (dlam, abs_dlam, dmu, abs_dmu, dcoords [3][N], abs_dcoords [3][N])."""
+    coords = _f64(mesh.coords)
+    conn = _i32(mesh.conn)
+    lam = _f64(lam)
+    mu = _f64(mu)
+    N, E = coords.shape[1], conn.shape[1]
+    dl, adl, dm, adm = np.zeros(E), np.zeros(E), np.zeros(E), np.zeros(E)
+    dx = np.zeros((3, N)) if want_coords else None
+    adx = np.zeros((3, N)) if want_coords else None
+    bf = _f64(body_force if body_force is not None else [0.0, 0.0, 0.0])
+    Gbar = None if Gbar is None else _f64(Gbar)
+    gbar = None if gbar is None else _f64(gbar)
+    _check(lib().fo_backward_p2_elasticity(N, E, _p(coords), _p(conn), _p(lam), _p(mu),
+                                           LOAD[load], _p(bf), _p(rowptr), _p(colind),
+                                           _p(Gbar), _p(gbar), _p(dl), _p(adl), _p(dm),
+                                           _p(adm), _p(dx), _p(adx)), "backward_p2")
+    return dl, adl, dm, adm, dx, adx

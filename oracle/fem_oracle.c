@@ -1,0 +1,915 @@
+/*
+ * fem_oracle.c -- plain, slow, FP64 CPU oracle for finite element assembly.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg load this library.  It shares no code, header, table or constant
+ * with the HIP library and includes nothing from it.
+ *
+ * What it computes (Cui, Guo, Liu, "GPU Accelerated Finite Element Assembly with
+ * Runtime Compilation"):
+ *   - Sec. 4.1, Eq. (1)-(3): the Galerkin system A x = b of the generalised Helmholtz
+ *     problem -div(kappa grad u) + c u = f with Neumann boundary conditions, using
+ *     Lagrange P1 elements; A_ij sums over the elements holding nodes i and j, b_i over
+ *     the elements holding node i.  Here kappa is a per-element scalar (the symmetric
+ *     positive definite sigma of Eq. (1) restricted to kappa*I) and c is the reaction
+ *     constant (lambda in Eq. (1)).
+ *   - Sec. 5 (sparse variant): the stored matrix keeps, per row, exactly the columns
+ *     of the nodes that share an element with the row's node (the paper's
+ *     gNbrNodeLen / gNbrNodeIdx arrays); here those lists are stored as CSR.
+ *   - Sec. 7 names higher-order approximations as the next step: isotropic linear
+ *     elasticity with Lagrange P2 tetrahedra, the same assembly structure with 3
+ *     interleaved components per node (dof = 3*node + component).
+ *
+ * How.  Wherever the method's quadrature is exact (affine elements, constant
+ * coefficients per element: every matrix term here), the oracle evaluates the exact
+ * integrals instead, by the simplex monomial formula
+ *     (1/|T|) int_T  prod_k lambda_k^{a_k}  =  d! prod_k a_k! / (|a| + d)! .
+ * The sin-product load is not polynomial, so its value is defined by the quadrature
+ * rule; the oracle derives each rule it uses from the exactness conditions it must meet
+ * (fo_quad_rule) rather than from a table.
+ * Gradients with respect to node coordinates use complex-step differentiation of the
+ * element routine (Squire & Trapp 1998), independent of any hand-derived adjoint.
+ *
+ * Conventions shared with the mesh generator (input format, not method):
+ *   coords SoA [dim][n_nodes]; conn SoA [npe][n_elems]; P2 local order: vertices
+ *   0..3, then edge nodes of edges (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).
+ *   load kinds: 0 = none, 1 = constant (per component), 2 = prod_a sin(pi x_a).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define FO_OK 0
+#define FO_ERR_ARG 1
+#define FO_ERR_NOTFOUND 2
+#define FO_ERR_OOM 3
+#define FO_ERR_RULE 4
+
+#define LOAD_NONE 0
+#define LOAD_CONST 1
+#define LOAD_SINPROD 2
+
+typedef double complex cplx;
+
+static const int P2_EDGE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+/* ------------------------------------------------------------------------------------
+ * Simplex monomial integrals (normalised by the simplex volume).
+ * ---------------------------------------------------------------------------------- */
+static double factorial(int n)
+{
+    double r = 1.0;
+    for (int i = 2; i <= n; ++i) r *= (double)i;
+    return r;
+}
+
+double fo_simplex_monomial(int d, const int *alpha)
+{
+    int total = 0;
+    double num = factorial(d);
+    for (int k = 0; k <= d; ++k) {
+        num *= factorial(alpha[k]);
+        total += alpha[k];
+    }
+    return num / factorial(total + d);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Quadrature rules on the reference simplex, in barycentric coordinates, weights
+ * summing to 1 (volume fractions).  The paper names no rule; these are the symmetric
+ * rules of the degrees the forms need, each obtained by solving its own exactness
+ * conditions.
+ * ---------------------------------------------------------------------------------- */
+
+/* Degree-5, 14-point tetrahedron rule: two 4-point orbits (a,a,a,1-3a) and one 6-point
+ * orbit (b,b,1/2-b,1/2-b).  The six unknowns (a1,w1,a2,w2,b,w3) are found by
+ * Gauss-Newton on the exactness equations of every monomial of degree <= 5. */
+static void orbit_points(const long double u[6], long double pts[14][4], long double w[14])
+{
+    int q = 0;
+    for (int orb = 0; orb < 2; ++orb) {
+        long double a = u[2 * orb], wt = u[2 * orb + 1];
+        for (int p = 0; p < 4; ++p, ++q) {
+            for (int k = 0; k < 4; ++k) pts[q][k] = (k == p) ? 1.0L - 3.0L * a : a;
+            w[q] = wt;
+        }
+    }
+    long double b = u[4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j, ++q) {
+            for (int k = 0; k < 4; ++k) pts[q][k] = (k == i || k == j) ? b : 0.5L - b;
+            w[q] = u[5];
+        }
+}
+
+/* d/d(orbit parameter) of each barycentric coordinate of each point */
+static void orbit_dpoints(long double dp[14][4])
+{
+    int q = 0;
+    for (int orb = 0; orb < 2; ++orb)
+        for (int p = 0; p < 4; ++p, ++q)
+            for (int k = 0; k < 4; ++k) dp[q][k] = (k == p) ? -3.0L : 1.0L;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j, ++q)
+            for (int k = 0; k < 4; ++k) dp[q][k] = (k == i || k == j) ? 1.0L : -1.0L;
+}
+
+static long double powl_int(long double x, int n)
+{
+    long double r = 1.0L;
+    for (int i = 0; i < n; ++i) r *= x;
+    return r;
+}
+
+static int solve_small(int n, long double *M, long double *rhs) /* M[n*n], in place */
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabsl(M[r * n + c]) > fabsl(M[piv * n + c])) piv = r;
+        if (M[piv * n + c] == 0.0L) return -1;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) {
+                long double t = M[c * n + k];
+                M[c * n + k] = M[piv * n + k];
+                M[piv * n + k] = t;
+            }
+            long double t = rhs[c];
+            rhs[c] = rhs[piv];
+            rhs[piv] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            long double f = M[r * n + c] / M[c * n + c];
+            for (int k = c; k < n; ++k) M[r * n + k] -= f * M[c * n + k];
+            rhs[r] -= f * rhs[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        long double s = rhs[c];
+        for (int k = c + 1; k < n; ++k) s -= M[c * n + k] * rhs[k];
+        rhs[c] = s / M[c * n + c];
+    }
+    return 0;
+}
+
+static int tet14_rule(double *bary, double *w)
+{
+    /* all exponent vectors of degree <= 5 in 4 barycentric variables */
+    int alphas[126][4];
+    int nm = 0;
+    for (int a0 = 0; a0 <= 5; ++a0)
+        for (int a1 = 0; a0 + a1 <= 5; ++a1)
+            for (int a2 = 0; a0 + a1 + a2 <= 5; ++a2)
+                for (int a3 = 0; a0 + a1 + a2 + a3 <= 5; ++a3) {
+                    alphas[nm][0] = a0;
+                    alphas[nm][1] = a1;
+                    alphas[nm][2] = a2;
+                    alphas[nm][3] = a3;
+                    ++nm;
+                }
+    long double u[6] = {0.1L, 0.07L, 0.3L, 0.11L, 0.05L, 0.04L};
+    long double dp[14][4];
+    orbit_dpoints(dp);
+    for (int it = 0; it < 100; ++it) {
+        long double pts[14][4], wq[14];
+        orbit_points(u, pts, wq);
+        long double JtJ[36] = {0}, Jtr[6] = {0};
+        for (int m = 0; m < nm; ++m) {
+            long double r = -(long double)fo_simplex_monomial(3, alphas[m]);
+            long double jac[6] = {0};
+            for (int q = 0; q < 14; ++q) {
+                long double mono = 1.0L, dmono = 0.0L;
+                for (int k = 0; k < 4; ++k) {
+                    int e = alphas[m][k];
+                    long double pk = powl_int(pts[q][k], e);
+                    long double dk = e ? e * powl_int(pts[q][k], e - 1) * dp[q][k] : 0.0L;
+                    dmono = dmono * pk + mono * dk;
+                    mono *= pk;
+                }
+                r += wq[q] * mono;
+                int par = (q < 4) ? 0 : (q < 8) ? 2 : 4; /* index of this orbit's point parameter */
+                jac[par] += wq[q] * dmono;
+                jac[par + 1] += mono;
+            }
+            for (int i = 0; i < 6; ++i) {
+                Jtr[i] += jac[i] * r;
+                for (int j = 0; j < 6; ++j) JtJ[i * 6 + j] += jac[i] * jac[j];
+            }
+        }
+        for (int i = 0; i < 6; ++i) Jtr[i] = -Jtr[i];
+        if (solve_small(6, JtJ, Jtr)) return -1;
+        long double step = 0.0L;
+        for (int i = 0; i < 6; ++i) {
+            u[i] += Jtr[i];
+            step = fmaxl(step, fabsl(Jtr[i]));
+        }
+        if (step < 1e-19L) break;
+    }
+    long double pts[14][4], wq[14];
+    orbit_points(u, pts, wq);
+    for (int q = 0; q < 14; ++q) {
+        for (int k = 0; k < 4; ++k) bary[q * 4 + k] = (double)pts[q][k];
+        w[q] = (double)wq[q];
+    }
+    return 14;
+}
+
+/* Returns the number of points, or -1 when no rule of that kind is provided. */
+int fo_quad_rule(int d, int degree, double *bary, double *w)
+{
+    if (d == 2 && degree <= 2) {
+        /* 3-point orbit (a,b,b), b = (1-a)/2, weights 1/3: exactness for lambda_0^2
+         * (mean 1/6) gives 3a^2 - 2a = 0; the interior root is a = 2/3. */
+        double a = 2.0 / 3.0, b = 0.5 * (1.0 - a);
+        for (int q = 0; q < 3; ++q) {
+            for (int k = 0; k < 3; ++k) bary[q * 3 + k] = (k == q) ? a : b;
+            w[q] = 1.0 / 3.0;
+        }
+        return 3;
+    }
+    if (d == 3 && degree <= 2) {
+        /* 4-point orbit (a,b,b,b), b = (1-a)/3, weights 1/4: exactness for lambda_0^2
+         * (mean 1/10) gives 4a^2 - 2a - 1/5 = 0; the root inside the simplex is taken. */
+        double a = (2.0 + sqrt(4.0 + 16.0 / 5.0)) / 8.0, b = (1.0 - a) / 3.0;
+        for (int q = 0; q < 4; ++q) {
+            for (int k = 0; k < 4; ++k) bary[q * 4 + k] = (k == q) ? a : b;
+            w[q] = 0.25;
+        }
+        return 4;
+    }
+    if (d == 3 && degree <= 5) return tet14_rule(bary, w);
+    return -1;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Sparsity pattern (Sec. 5, sparse variant): row dof r holds every dof sharing an
+ * element with it, columns ascending, diagonal included, explicit zeros kept.
+ * ---------------------------------------------------------------------------------- */
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Returns nnz (>= 0) or a negative error.  rowptr has n_nodes*ncomp + 1 entries.
+ * When colind is NULL only rowptr is filled. */
+int64_t fo_pattern(int npe, int ncomp, int64_t n_nodes, int64_t n_elems, const int32_t *conn,
+                   int64_t *rowptr, int32_t *colind)
+{
+    if (npe <= 0 || ncomp <= 0 || n_nodes < 0 || n_elems < 0 || !rowptr) return -FO_ERR_ARG;
+    int64_t *n2e_ptr = calloc((size_t)n_nodes + 1, sizeof(int64_t));
+    int64_t *fill = calloc((size_t)n_nodes + 1, sizeof(int64_t));
+    int64_t *n2e = malloc(sizeof(int64_t) * (size_t)(n_elems * npe + 1));
+    if (!n2e_ptr || !fill || !n2e) {
+        free(n2e_ptr);
+        free(fill);
+        free(n2e);
+        return -FO_ERR_OOM;
+    }
+    for (int64_t e = 0; e < n_elems; ++e)
+        for (int k = 0; k < npe; ++k) {
+            int32_t v = conn[k * n_elems + e];
+            if (v < 0 || v >= n_nodes) {
+                free(n2e_ptr);
+                free(fill);
+                free(n2e);
+                return -FO_ERR_ARG;
+            }
+            n2e_ptr[v + 1]++;
+        }
+    for (int64_t n = 0; n < n_nodes; ++n) n2e_ptr[n + 1] += n2e_ptr[n];
+    for (int64_t e = 0; e < n_elems; ++e)
+        for (int k = 0; k < npe; ++k) {
+            int32_t v = conn[k * n_elems + e];
+            n2e[n2e_ptr[v] + fill[v]++] = e;
+        }
+    int64_t maxdeg = 0;
+    for (int64_t n = 0; n < n_nodes; ++n)
+        if (n2e_ptr[n + 1] - n2e_ptr[n] > maxdeg) maxdeg = n2e_ptr[n + 1] - n2e_ptr[n];
+    int32_t *tmp = malloc(sizeof(int32_t) * (size_t)(maxdeg * npe + 1));
+    if (!tmp) {
+        free(n2e_ptr);
+        free(fill);
+        free(n2e);
+        return -FO_ERR_OOM;
+    }
+    rowptr[0] = 0;
+    for (int64_t n = 0; n < n_nodes; ++n) {
+        int64_t cnt = 0;
+        for (int64_t t = n2e_ptr[n]; t < n2e_ptr[n + 1]; ++t)
+            for (int k = 0; k < npe; ++k) tmp[cnt++] = conn[k * n_elems + n2e[t]];
+        qsort(tmp, (size_t)cnt, sizeof(int32_t), cmp_i32);
+        int64_t u = 0;
+        for (int64_t t = 0; t < cnt; ++t)
+            if (u == 0 || tmp[t] != tmp[u - 1]) tmp[u++] = tmp[t];
+        for (int a = 0; a < ncomp; ++a) {
+            int64_t row = n * ncomp + a;
+            rowptr[row + 1] = rowptr[row] + u * ncomp;
+            if (colind)
+                for (int64_t t = 0; t < u; ++t)
+                    for (int b = 0; b < ncomp; ++b)
+                        colind[rowptr[row] + t * ncomp + b] = (int32_t)(tmp[t] * ncomp + b);
+        }
+    }
+    int64_t nnz = rowptr[n_nodes * ncomp];
+    free(tmp);
+    free(n2e_ptr);
+    free(fill);
+    free(n2e);
+    return nnz;
+}
+
+/* position of (row, col) in the CSR arrays, by binary search; -1 when absent */
+static int64_t find_slot(const int64_t *rowptr, const int32_t *colind, int64_t row, int32_t col)
+{
+    int64_t lo = rowptr[row], hi = rowptr[row + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (colind[mid] < col) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < rowptr[row + 1] && colind[lo] == col) return lo;
+    return -1;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Affine simplex geometry.  Vertices x[k][a], k = 0..d.
+ * J[a][k] = x[k+1][a] - x[0][a];  grad lambda_k = row (k-1) of J^{-1} for k >= 1,
+ * grad lambda_0 = -(sum of those rows).  Real and complex versions.
+ * ---------------------------------------------------------------------------------- */
+static double geom_real(int d, const double x[4][3], double B[4][3])
+{
+    double J[3][3], inv[3][3], det;
+    for (int a = 0; a < d; ++a)
+        for (int k = 0; k < d; ++k) J[a][k] = x[k + 1][a] - x[0][a];
+    if (d == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        inv[0][0] = J[1][1] / det;
+        inv[0][1] = -J[0][1] / det;
+        inv[1][0] = -J[1][0] / det;
+        inv[1][1] = J[0][0] / det;
+    } else {
+        double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        inv[0][0] = c00 / det;
+        inv[1][0] = c01 / det;
+        inv[2][0] = c02 / det;
+        inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    for (int a = 0; a < d; ++a) {
+        double s = 0.0;
+        for (int k = 1; k <= d; ++k) {
+            B[k][a] = inv[k - 1][a];
+            s += inv[k - 1][a];
+        }
+        B[0][a] = -s;
+    }
+    return det;
+}
+
+static cplx geom_cplx(int d, cplx x[4][3], cplx B[4][3])
+{
+    cplx J[3][3], inv[3][3], det;
+    for (int a = 0; a < d; ++a)
+        for (int k = 0; k < d; ++k) J[a][k] = x[k + 1][a] - x[0][a];
+    if (d == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        inv[0][0] = J[1][1] / det;
+        inv[0][1] = -J[0][1] / det;
+        inv[1][0] = -J[1][0] / det;
+        inv[1][1] = J[0][0] / det;
+    } else {
+        cplx c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        cplx c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        cplx c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        inv[0][0] = c00 / det;
+        inv[1][0] = c01 / det;
+        inv[2][0] = c02 / det;
+        inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    for (int a = 0; a < d; ++a) {
+        cplx s = 0.0;
+        for (int k = 1; k <= d; ++k) {
+            B[k][a] = inv[k - 1][a];
+            s += inv[k - 1][a];
+        }
+        B[0][a] = -s;
+    }
+    return det;
+}
+
+int fo_signed_volumes(int d, int64_t n_nodes, int64_t n_elems, const double *coords,
+                      const int32_t *conn, double *out)
+{
+    if (d != 2 && d != 3) return FO_ERR_ARG;
+    for (int64_t e = 0; e < n_elems; ++e) {
+        double x[4][3], B[4][3];
+        for (int k = 0; k <= d; ++k)
+            for (int a = 0; a < d; ++a) x[k][a] = coords[a * n_nodes + conn[k * n_elems + e]];
+        out[e] = geom_real(d, x, B) / factorial(d);
+    }
+    return FO_OK;
+}
+
+/* ------------------------------------------------------------------------------------
+ * P1 element:  A_ij = kappa |T| grad l_i . grad l_j  +  c int_T l_i l_j,
+ * int_T l_i l_j = |T| (1 + delta_ij) d! / (d+2)!   (monomial formula, Eq. (2) terms).
+ * Load b_i = int_T f l_i: constant f -> f |T| / (d+1); sin product -> quadrature.
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    int n;
+    double bary[14 * 4];
+    double w[14];
+} rule_t;
+
+static double mass_p1_ref(int d, int i, int j) /* (1/|T|) int l_i l_j */
+{
+    int alpha[4] = {0, 0, 0, 0};
+    alpha[i] += 1;
+    alpha[j] += 1;
+    return fo_simplex_monomial(d, alpha);
+}
+
+static double f_sinprod(int d, const double *xq)
+{
+    double f = 1.0;
+    for (int a = 0; a < d; ++a) f *= sin(M_PI * xq[a]);
+    return f;
+}
+
+static cplx f_sinprod_c(int d, const cplx *xq)
+{
+    cplx f = 1.0;
+    for (int a = 0; a < d; ++a) f *= csin(M_PI * xq[a]);
+    return f;
+}
+
+static void p1_element_real(int d, const double x[4][3], double kappa, double c, int load,
+                            double fconst, const rule_t *rule, double A[16], double bvec[4],
+                            double *vol_out)
+{
+    double B[4][3];
+    double det = geom_real(d, x, B);
+    double vol = fabs(det) / factorial(d);
+    int np = d + 1;
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+            double g = 0.0;
+            for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
+            A[i * np + j] = kappa * vol * g + c * vol * mass_p1_ref(d, i, j);
+        }
+    for (int i = 0; i < np; ++i) bvec[i] = 0.0;
+    if (load == LOAD_CONST) {
+        for (int i = 0; i < np; ++i) bvec[i] = fconst * vol / (double)(d + 1);
+    } else if (load == LOAD_SINPROD) {
+        for (int q = 0; q < rule->n; ++q) {
+            const double *lam = &rule->bary[q * np];
+            double xq[3] = {0, 0, 0};
+            for (int k = 0; k < np; ++k)
+                for (int a = 0; a < d; ++a) xq[a] += lam[k] * x[k][a];
+            double fq = f_sinprod(d, xq);
+            for (int i = 0; i < np; ++i) bvec[i] += vol * rule->w[q] * fq * lam[i];
+        }
+    }
+    if (vol_out) *vol_out = vol;
+}
+
+static int p1_rule(int d, rule_t *rule)
+{
+    rule->n = fo_quad_rule(d, 2, rule->bary, rule->w);
+    return rule->n > 0 ? FO_OK : FO_ERR_RULE;
+}
+
+int fo_element_p1(int d, const double *xv, double kappa, double c, double *A)
+{
+    if (d != 2 && d != 3) return FO_ERR_ARG;
+    double x[4][3] = {{0}};
+    for (int k = 0; k <= d; ++k)
+        for (int a = 0; a < d; ++a) x[k][a] = xv[k * d + a];
+    double b[4];
+    p1_element_real(d, x, kappa, c, LOAD_NONE, 0.0, NULL, A, b, NULL);
+    return FO_OK;
+}
+
+int fo_assemble_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords,
+                   const int32_t *conn, const double *kappa, double c, int load,
+                   const double *load_const, const int64_t *rowptr, const int32_t *colind,
+                   double *values, double *rhs, double *abs_values, double *abs_rhs)
+{
+    if (d != 2 && d != 3) return FO_ERR_ARG;
+    rule_t rule;
+    if (p1_rule(d, &rule)) return FO_ERR_RULE;
+    int64_t nnz = rowptr[n_nodes];
+    if (values) memset(values, 0, sizeof(double) * (size_t)nnz);
+    if (abs_values) memset(abs_values, 0, sizeof(double) * (size_t)nnz);
+    if (rhs) memset(rhs, 0, sizeof(double) * (size_t)n_nodes);
+    if (abs_rhs) memset(abs_rhs, 0, sizeof(double) * (size_t)n_nodes);
+    double fconst = load_const ? load_const[0] : 0.0;
+    int np = d + 1;
+    for (int64_t e = 0; e < n_elems; ++e) {
+        double x[4][3], A[16], b[4];
+        int32_t v[4];
+        for (int k = 0; k < np; ++k) {
+            v[k] = conn[k * n_elems + e];
+            for (int a = 0; a < d; ++a) x[k][a] = coords[a * n_nodes + v[k]];
+        }
+        p1_element_real(d, x, kappa[e], c, load, fconst, &rule, A, b, NULL);
+        for (int i = 0; i < np; ++i) {
+            for (int j = 0; j < np; ++j) {
+                int64_t s = find_slot(rowptr, colind, v[i], v[j]);
+                if (s < 0) return FO_ERR_NOTFOUND;
+                if (values) values[s] += A[i * np + j];
+                if (abs_values) abs_values[s] += fabs(A[i * np + j]);
+            }
+            if (rhs) rhs[v[i]] += b[i];
+            if (abs_rhs) abs_rhs[v[i]] += fabs(b[i]);
+        }
+    }
+    return FO_OK;
+}
+
+/* Complex version of the P1 element functional
+ *   L_e(x) = sum_ij Gb_ij A_ij(x) + sum_i gb_i b_i(x),
+ * with |det J| continued analytically as det * sign(Re det). */
+static cplx p1_local_L_c(int d, cplx x[4][3], double kappa, double c, int load, double fconst,
+                         const rule_t *rule, const double *Gb, const double *gb)
+{
+    cplx B[4][3];
+    cplx det = geom_cplx(d, x, B);
+    cplx vol = det * (creal(det) > 0 ? 1.0 : -1.0) / factorial(d);
+    int np = d + 1;
+    cplx L = 0.0;
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+            cplx g = 0.0;
+            for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
+            L += Gb[i * np + j] * (kappa * vol * g + c * vol * mass_p1_ref(d, i, j));
+        }
+    if (load == LOAD_CONST) {
+        for (int i = 0; i < np; ++i) L += gb[i] * fconst * vol / (double)(d + 1);
+    } else if (load == LOAD_SINPROD) {
+        for (int q = 0; q < rule->n; ++q) {
+            const double *lam = &rule->bary[q * np];
+            cplx xq[3] = {0, 0, 0};
+            for (int k = 0; k < np; ++k)
+                for (int a = 0; a < d; ++a) xq[a] += lam[k] * x[k][a];
+            cplx fq = f_sinprod_c(d, xq);
+            for (int i = 0; i < np; ++i) L += gb[i] * vol * rule->w[q] * fq * lam[i];
+        }
+    }
+    return L;
+}
+
+#define CSTEP 1e-30
+
+/* dL/dkappa_e = <Gbar_e, |T| grad l grad l^T> (L is linear in kappa);
+ * dL/dx by complex step of the element functional, scattered to nodes.
+ * abs_dcoords[a][n] accumulates, per node, the largest |dL_e/dx| entry of every element
+ * holding n (an element-level magnitude for the comparison tolerance). */
+int fo_backward_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords,
+                   const int32_t *conn, const double *kappa, double c, int load,
+                   const double *load_const, const int64_t *rowptr, const int32_t *colind,
+                   const double *Gbar, const double *gbar, double *dkappa, double *abs_dkappa,
+                   double *dcoords, double *abs_dcoords)
+{
+    if (d != 2 && d != 3) return FO_ERR_ARG;
+    rule_t rule;
+    if (p1_rule(d, &rule)) return FO_ERR_RULE;
+    int np = d + 1;
+    double fconst = load_const ? load_const[0] : 0.0;
+    if (dcoords) memset(dcoords, 0, sizeof(double) * (size_t)(d * n_nodes));
+    if (abs_dcoords) memset(abs_dcoords, 0, sizeof(double) * (size_t)(d * n_nodes));
+    for (int64_t e = 0; e < n_elems; ++e) {
+        double x[4][3], Gb[16] = {0}, gb[4] = {0};
+        int32_t v[4];
+        for (int k = 0; k < np; ++k) {
+            v[k] = conn[k * n_elems + e];
+            for (int a = 0; a < d; ++a) x[k][a] = coords[a * n_nodes + v[k]];
+        }
+        for (int i = 0; i < np; ++i) {
+            for (int j = 0; j < np; ++j) {
+                int64_t s = find_slot(rowptr, colind, v[i], v[j]);
+                if (s < 0) return FO_ERR_NOTFOUND;
+                Gb[i * np + j] = Gbar ? Gbar[s] : 0.0;
+            }
+            gb[i] = gbar ? gbar[v[i]] : 0.0;
+        }
+        if (dkappa || abs_dkappa) {
+            double B[4][3];
+            double vol = fabs(geom_real(d, x, B)) / factorial(d);
+            double acc = 0.0, aacc = 0.0;
+            for (int i = 0; i < np; ++i)
+                for (int j = 0; j < np; ++j) {
+                    double g = 0.0;
+                    for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
+                    acc += Gb[i * np + j] * vol * g;
+                    aacc += fabs(Gb[i * np + j] * vol * g);
+                }
+            if (dkappa) dkappa[e] = acc;
+            if (abs_dkappa) abs_dkappa[e] = aacc;
+        }
+        if (dcoords || abs_dcoords) {
+            double grad[4][3], gmax = 0.0;
+            for (int k = 0; k < np; ++k)
+                for (int a = 0; a < d; ++a) {
+                    cplx xc[4][3];
+                    for (int kk = 0; kk < np; ++kk)
+                        for (int aa = 0; aa < d; ++aa) xc[kk][aa] = x[kk][aa];
+                    xc[k][a] += I * CSTEP;
+                    cplx L = p1_local_L_c(d, xc, kappa[e], c, load, fconst, &rule, Gb, gb);
+                    grad[k][a] = cimag(L) / CSTEP;
+                    if (fabs(grad[k][a]) > gmax) gmax = fabs(grad[k][a]);
+                }
+            for (int k = 0; k < np; ++k)
+                for (int a = 0; a < d; ++a) {
+                    if (dcoords) dcoords[a * n_nodes + v[k]] += grad[k][a];
+                    if (abs_dcoords) abs_dcoords[a * n_nodes + v[k]] += gmax;
+                }
+        }
+    }
+    return FO_OK;
+}
+
+/* ------------------------------------------------------------------------------------
+ * P2 tetrahedron, isotropic linear elasticity (Sec. 7 outlook: higher order).
+ *   phi_v = l_v (2 l_v - 1)          grad phi_v = (4 l_v - 1) grad l_v
+ *   phi_vw = 4 l_v l_w               grad phi_vw = 4 l_w grad l_v + 4 l_v grad l_w
+ * so grad phi_i = sum_k P_ik(l) grad l_k with P_ik linear in l.  With
+ *   G^{ab}_ij = int_T d_a phi_i d_b phi_j = sum_kl B_ka B_lb int_T P_ik P_jl,
+ * the bilinear form  int lam div u div v + 2 mu eps(u):eps(v)  gives, for test dof
+ * (i,a) and trial dof (j,b),
+ *   K = lam G^{ab}_ij + mu G^{ba}_ij + mu delta_ab sum_c G^{cc}_ij.
+ * ---------------------------------------------------------------------------------- */
+/* P_ik as coefficients over {1, l_0, l_1, l_2, l_3} */
+static void p2_gradpoly(double P[10][4][5])
+{
+    memset(P, 0, sizeof(double) * 10 * 4 * 5);
+    for (int v = 0; v < 4; ++v) {
+        P[v][v][0] = -1.0;
+        P[v][v][1 + v] = 4.0;
+    }
+    for (int e = 0; e < 6; ++e) {
+        int v = P2_EDGE[e][0], w = P2_EDGE[e][1];
+        P[4 + e][v][1 + w] = 4.0;
+        P[4 + e][w][1 + v] = 4.0;
+    }
+}
+
+/* (1/|T|) int_T p q for two polynomials given over {1, l_0..l_3} */
+static double int_lin_lin(const double p[5], const double q[5])
+{
+    double s = 0.0;
+    for (int m = 0; m < 5; ++m)
+        for (int n = 0; n < 5; ++n) {
+            if (p[m] == 0.0 || q[n] == 0.0) continue;
+            int alpha[4] = {0, 0, 0, 0};
+            if (m) alpha[m - 1] += 1;
+            if (n) alpha[n - 1] += 1;
+            s += p[m] * q[n] * fo_simplex_monomial(3, alpha);
+        }
+    return s;
+}
+
+static double IREF[10][4][10][4]; /* (1/|T|) int P_ik P_jl */
+static double PHI_MEAN[10];      /* (1/|T|) int phi_i */
+static int p2_tables_ready = 0;
+
+static void p2_tables(void)
+{
+    if (p2_tables_ready) return;
+    double P[10][4][5];
+    p2_gradpoly(P);
+    for (int i = 0; i < 10; ++i)
+        for (int k = 0; k < 4; ++k)
+            for (int j = 0; j < 10; ++j)
+                for (int l = 0; l < 4; ++l) IREF[i][k][j][l] = int_lin_lin(P[i][k], P[j][l]);
+    for (int v = 0; v < 4; ++v) {
+        int a2[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
+        a2[v] = 2;
+        a1[v] = 1;
+        PHI_MEAN[v] = 2.0 * fo_simplex_monomial(3, a2) - fo_simplex_monomial(3, a1);
+    }
+    for (int e = 0; e < 6; ++e) {
+        int a[4] = {0, 0, 0, 0};
+        a[P2_EDGE[e][0]] = 1;
+        a[P2_EDGE[e][1]] = 1;
+        PHI_MEAN[4 + e] = 4.0 * fo_simplex_monomial(3, a);
+    }
+    p2_tables_ready = 1;
+}
+
+/* G[i][a][j][b] (real), returns |T| */
+static double p2_gram_real(const double x[4][3], double G[10][3][10][3])
+{
+    double B[4][3];
+    double vol = fabs(geom_real(3, x, B)) / 6.0;
+    for (int i = 0; i < 10; ++i)
+        for (int j = 0; j < 10; ++j)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double s = 0.0;
+                    for (int k = 0; k < 4; ++k)
+                        for (int l = 0; l < 4; ++l) s += B[k][a] * B[l][b] * IREF[i][k][j][l];
+                    G[i][a][j][b] = vol * s;
+                }
+    return vol;
+}
+
+static cplx p2_gram_cplx(cplx x[4][3], cplx G[10][3][10][3])
+{
+    cplx B[4][3];
+    cplx det = geom_cplx(3, x, B);
+    cplx vol = det * (creal(det) > 0 ? 1.0 : -1.0) / 6.0;
+    for (int i = 0; i < 10; ++i)
+        for (int j = 0; j < 10; ++j)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    cplx s = 0.0;
+                    for (int k = 0; k < 4; ++k)
+                        for (int l = 0; l < 4; ++l) s += B[k][a] * B[l][b] * IREF[i][k][j][l];
+                    G[i][a][j][b] = vol * s;
+                }
+    return vol;
+}
+
+/* K^lam and K^mu split: K = lam*Kl + mu*Km, row (i,a) -> 3i+a, col (j,b) -> 3j+b */
+static void p2_split_real(double G[10][3][10][3], double Kl[900], double Km[900])
+{
+    for (int i = 0; i < 10; ++i)
+        for (int a = 0; a < 3; ++a)
+            for (int j = 0; j < 10; ++j)
+                for (int b = 0; b < 3; ++b) {
+                    int r = 3 * i + a, s = 3 * j + b;
+                    double tr = G[i][0][j][0] + G[i][1][j][1] + G[i][2][j][2];
+                    Kl[r * 30 + s] = G[i][a][j][b];
+                    Km[r * 30 + s] = G[i][b][j][a] + (a == b ? tr : 0.0);
+                }
+}
+
+int fo_element_p2_elasticity(const double *xv, double lam, double mu, double *K)
+{
+    p2_tables();
+    double x[4][3], G[10][3][10][3], Kl[900], Km[900];
+    for (int k = 0; k < 4; ++k)
+        for (int a = 0; a < 3; ++a) x[k][a] = xv[k * 3 + a];
+    p2_gram_real(x, G);
+    p2_split_real(G, Kl, Km);
+    for (int r = 0; r < 900; ++r) K[r] = lam * Kl[r] + mu * Km[r];
+    return FO_OK;
+}
+
+/* (1/|T|) int phi_i for the 10 P2 basis functions */
+int fo_p2_phi_mean(double *out)
+{
+    p2_tables();
+    for (int i = 0; i < 10; ++i) out[i] = PHI_MEAN[i];
+    return FO_OK;
+}
+
+int fo_assemble_p2_elasticity(int64_t n_nodes, int64_t n_elems, const double *coords,
+                              const int32_t *conn, const double *lam, const double *mu,
+                              int load, const double *body_force, const int64_t *rowptr,
+                              const int32_t *colind, double *values, double *rhs,
+                              double *abs_values, double *abs_rhs)
+{
+    if (load != LOAD_NONE && load != LOAD_CONST) return FO_ERR_ARG;
+    p2_tables();
+    int64_t nrows = 3 * n_nodes, nnz = rowptr[nrows];
+    if (values) memset(values, 0, sizeof(double) * (size_t)nnz);
+    if (abs_values) memset(abs_values, 0, sizeof(double) * (size_t)nnz);
+    if (rhs) memset(rhs, 0, sizeof(double) * (size_t)nrows);
+    if (abs_rhs) memset(abs_rhs, 0, sizeof(double) * (size_t)nrows);
+    static double G[10][3][10][3];
+    double Kl[900], Km[900];
+    for (int64_t e = 0; e < n_elems; ++e) {
+        double x[4][3];
+        int32_t v[10];
+        for (int k = 0; k < 10; ++k) v[k] = conn[k * n_elems + e];
+        for (int k = 0; k < 4; ++k)
+            for (int a = 0; a < 3; ++a) x[k][a] = coords[a * n_nodes + v[k]];
+        double vol = p2_gram_real(x, G);
+        p2_split_real(G, Kl, Km);
+        for (int i = 0; i < 10; ++i)
+            for (int a = 0; a < 3; ++a) {
+                int64_t row = 3 * (int64_t)v[i] + a;
+                for (int j = 0; j < 10; ++j)
+                    for (int b = 0; b < 3; ++b) {
+                        int r = 3 * i + a, s = 3 * j + b;
+                        double val = lam[e] * Kl[r * 30 + s] + mu[e] * Km[r * 30 + s];
+                        int64_t slot = find_slot(rowptr, colind, row, (int32_t)(3 * v[j] + b));
+                        if (slot < 0) return FO_ERR_NOTFOUND;
+                        if (values) values[slot] += val;
+                        if (abs_values) abs_values[slot] += fabs(val);
+                    }
+                if (load == LOAD_CONST) {
+                    double bv = body_force[a] * vol * PHI_MEAN[i];
+                    if (rhs) rhs[row] += bv;
+                    if (abs_rhs) abs_rhs[row] += fabs(bv);
+                }
+            }
+    }
+    return FO_OK;
+}
+
+static cplx p2_local_L_c(cplx x[4][3], double lam, double mu, int load, const double *bf,
+                         const double *Gb, const double *gb)
+{
+    static cplx G[10][3][10][3];
+    cplx vol = p2_gram_cplx(x, G);
+    cplx L = 0.0;
+    for (int i = 0; i < 10; ++i)
+        for (int a = 0; a < 3; ++a) {
+            for (int j = 0; j < 10; ++j)
+                for (int b = 0; b < 3; ++b) {
+                    cplx tr = G[i][0][j][0] + G[i][1][j][1] + G[i][2][j][2];
+                    cplx k = lam * G[i][a][j][b] + mu * G[i][b][j][a] + (a == b ? mu * tr : 0.0);
+                    L += Gb[(3 * i + a) * 30 + 3 * j + b] * k;
+                }
+            if (load == LOAD_CONST) L += gb[3 * i + a] * bf[a] * vol * PHI_MEAN[i];
+        }
+    return L;
+}
+
+int fo_backward_p2_elasticity(int64_t n_nodes, int64_t n_elems, const double *coords,
+                              const int32_t *conn, const double *lam, const double *mu,
+                              int load, const double *body_force, const int64_t *rowptr,
+                              const int32_t *colind, const double *Gbar, const double *gbar,
+                              double *dlam, double *abs_dlam, double *dmu, double *abs_dmu,
+                              double *dcoords, double *abs_dcoords)
+{
+    if (load != LOAD_NONE && load != LOAD_CONST) return FO_ERR_ARG;
+    p2_tables();
+    if (dcoords) memset(dcoords, 0, sizeof(double) * (size_t)(3 * n_nodes));
+    if (abs_dcoords) memset(abs_dcoords, 0, sizeof(double) * (size_t)(3 * n_nodes));
+    static double G[10][3][10][3];
+    double Kl[900], Km[900], Gb[900], gb[30];
+    for (int64_t e = 0; e < n_elems; ++e) {
+        double x[4][3];
+        int32_t v[10];
+        for (int k = 0; k < 10; ++k) v[k] = conn[k * n_elems + e];
+        for (int k = 0; k < 4; ++k)
+            for (int a = 0; a < 3; ++a) x[k][a] = coords[a * n_nodes + v[k]];
+        for (int i = 0; i < 10; ++i)
+            for (int a = 0; a < 3; ++a) {
+                int64_t row = 3 * (int64_t)v[i] + a;
+                gb[3 * i + a] = gbar ? gbar[row] : 0.0;
+                for (int j = 0; j < 10; ++j)
+                    for (int b = 0; b < 3; ++b) {
+                        int64_t slot = find_slot(rowptr, colind, row, (int32_t)(3 * v[j] + b));
+                        if (slot < 0) return FO_ERR_NOTFOUND;
+                        Gb[(3 * i + a) * 30 + 3 * j + b] = Gbar ? Gbar[slot] : 0.0;
+                    }
+            }
+        if (dlam || dmu || abs_dlam || abs_dmu) {
+            p2_gram_real(x, G);
+            p2_split_real(G, Kl, Km);
+            double sl = 0, sm = 0, al = 0, am = 0;
+            for (int r = 0; r < 900; ++r) {
+                sl += Gb[r] * Kl[r];
+                sm += Gb[r] * Km[r];
+                al += fabs(Gb[r] * Kl[r]);
+                am += fabs(Gb[r] * Km[r]);
+            }
+            if (dlam) dlam[e] = sl;
+            if (dmu) dmu[e] = sm;
+            if (abs_dlam) abs_dlam[e] = al;
+            if (abs_dmu) abs_dmu[e] = am;
+        }
+        if (dcoords || abs_dcoords) {
+            double grad[4][3], gmax = 0.0;
+            for (int k = 0; k < 4; ++k)
+                for (int a = 0; a < 3; ++a) {
+                    cplx xc[4][3];
+                    for (int kk = 0; kk < 4; ++kk)
+                        for (int aa = 0; aa < 3; ++aa) xc[kk][aa] = x[kk][aa];
+                    xc[k][a] += I * CSTEP;
+                    cplx L = p2_local_L_c(xc, lam[e], mu[e], load, body_force, Gb, gb);
+                    grad[k][a] = cimag(L) / CSTEP;
+                    if (fabs(grad[k][a]) > gmax) gmax = fabs(grad[k][a]);
+                }
+            /* edge nodes carry no geometry (they sit at the midpoints); the element's
+             * shape depends on the 4 vertices only */
+            for (int k = 0; k < 4; ++k)
+                for (int a = 0; a < 3; ++a) {
+                    if (dcoords) dcoords[a * n_nodes + v[k]] += grad[k][a];
+                    if (abs_dcoords) abs_dcoords[a * n_nodes + v[k]] += gmax;
+                }
+        }
+    }
+    return FO_OK;
+}

@@ -1,0 +1,79 @@
+"""Helpers shared by the tests (no assembly arithmetic lives here)."""
+
+from __future__ import annotations
+
+import os
+from fractions import Fraction
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def read_reference_elements():
+    out = {}
+    with open(os.path.join(GOLDEN, "reference_elements.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, scale, rest = line.split(None, 2)
+            rows = [[float(v) for v in r.split()] for r in rest.split(";")]
+            out[name] = float(Fraction(scale)) * np.array(rows)
+    return out
+
+
+def read_paper_values():
+    out = {}
+    with open(os.path.join(GOLDEN, "paper_values.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split()
+            out[k] = int(v)
+    return out
+
+
+def duffy_rule(d: int, n: int = 12):
+    """Collapsed-coordinate Gauss-Legendre rule on the reference simplex
+    {x_i >= 0, sum x_i <= 1}: returns (points [m][d], weights [m]) with weights
+    summing to the simplex volume 1/d!.  Independent of the oracle's rules."""
+    g, w = np.polynomial.legendre.leggauss(n)
+    g = 0.5 * (g + 1.0)
+    w = 0.5 * w
+    if d == 2:
+        u, v = np.meshgrid(g, g, indexing="ij")
+        wu, wv = np.meshgrid(w, w, indexing="ij")
+        x = u
+        y = (1 - u) * v
+        wt = wu * wv * (1 - u)
+        return np.stack([x.ravel(), y.ravel()], 1), wt.ravel()
+    u, v, s = np.meshgrid(g, g, g, indexing="ij")
+    wu, wv, ws = np.meshgrid(w, w, w, indexing="ij")
+    x = u
+    y = (1 - u) * v
+    z = (1 - u) * (1 - v) * s
+    wt = wu * wv * ws * (1 - u) ** 2 * (1 - v)
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], 1), wt.ravel()
+
+
+def bary_of_ref(pts):
+    """reference coordinates [m][d] -> barycentric [m][d+1] (lambda_0 = 1 - sum)."""
+    return np.concatenate([1.0 - pts.sum(1, keepdims=True), pts], axis=1)
+
+
+def scaled_close(got, ref, scale, rtol):
+    """Per-entry |got-ref| <= rtol*max(|ref|, scale) and normwise check.
+    Returns (ok, worst ratio)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.asarray(scale, dtype=np.float64)
+    denom = np.maximum(np.abs(ref), scale)
+    denom = np.where(denom == 0, 1.0, denom)
+    err = np.abs(got - ref)
+    ratio = err / denom
+    worst = float(ratio.max()) if ratio.size else 0.0
+    normwise = float(err.max()) <= rtol * max(float(np.abs(ref).max()) if ref.size else 0.0, 1e-300) \
+        if ref.size else True
+    return (worst <= rtol) and normwise, worst

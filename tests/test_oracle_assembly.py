@@ -1,0 +1,197 @@
+"""Pins of the oracle's global assembly against closed forms and invariants
+(Sec. 4.1, Eq. (1)-(3); Neumann problem, so no boundary rows are modified)."""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import meshgen
+import oracle
+from tests._util import duffy_rule
+
+
+def _csr(rowptr, colind, vals, nrows):
+    return sp.csr_matrix((vals, colind, rowptr), shape=(nrows, nrows))
+
+
+def _assemble(m, kappa, c, load="none", lc=None):
+    rowptr, colind = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+    vals, rhs, av, ar = oracle.assemble_p1(m, kappa, c, load, lc, rowptr, colind)
+    return _csr(rowptr, colind, vals, m.n_nodes), rhs
+
+
+def _interior(m):
+    x = m.coords
+    tol = 1e-12
+    return np.all((x > tol) & (x < 1 - tol), axis=0)
+
+
+def test_meshes_are_not_inverted():
+    """Jittered meshes keep every element's orientation (the generator's validity)."""
+    for m0, m in [(meshgen.square_tri(32, jitter=0), meshgen.square_tri(32)),
+                  (meshgen.cube_tet(16, jitter=0), meshgen.cube_tet(16)),
+                  (meshgen.cube_tet(8, 2, jitter=0), meshgen.cube_tet(8, 2))]:
+        v0 = oracle.signed_volumes(m0)
+        v1 = oracle.signed_volumes(m)
+        assert np.all(np.sign(v0) == np.sign(v1))
+        assert np.min(v1 / v0) > 0.01
+        assert abs(np.abs(v1).sum() - 1.0) < 1e-12
+
+
+@pytest.mark.slow
+def test_full_size_3d_mesh_not_inverted():
+    m0, m = meshgen.cube_tet(64, jitter=0), meshgen.cube_tet(64)
+    r = oracle.signed_volumes(m) / oracle.signed_volumes(m0)
+    assert r.min() > 0.01
+
+
+def test_unjittered_2d_five_point_stencil():
+    n = 8
+    m = meshgen.square_tri(n, jitter=0)
+    K, _ = _assemble(m, np.ones(m.n_elems), 0.0)
+    i, j = 3, 4
+    r = i + (n + 1) * j
+    row = K.getrow(r).toarray().ravel()
+    nz = row[K.indices[K.indptr[r]:K.indptr[r + 1]]]
+    assert sorted(np.round(nz, 14)) == [-1, -1, -1, -1, 0, 0, 4]
+    for off in (1, -1, n + 1, -(n + 1)):
+        assert row[r + off] == pytest.approx(-1.0, abs=1e-14)
+
+
+def test_unjittered_3d_seven_point_stencil():
+    n = 6
+    h = 1.0 / n
+    m = meshgen.cube_tet(n, jitter=0)
+    K, _ = _assemble(m, np.ones(m.n_elems), 0.0)
+    s = n + 1
+    r = 3 + s * (2 + s * 3)
+    row = K.getrow(r).toarray().ravel()
+    nz = row[K.indices[K.indptr[r]:K.indptr[r + 1]]] / h
+    assert len(nz) == 15
+    assert sorted(np.round(nz, 12)) == [-1] * 6 + [0] * 8 + [6]
+    for off in (1, s, s * s):
+        assert row[r + off] == pytest.approx(-h, abs=1e-15)
+        assert row[r - off] == pytest.approx(-h, abs=1e-15)
+
+
+@pytest.mark.parametrize("kind", ["tri", "tet"])
+def test_mass_row_sums_unjittered(kind):
+    n = 6
+    m = meshgen.square_tri(n, jitter=0) if kind == "tri" else meshgen.cube_tet(n, jitter=0)
+    M, _ = _assemble(m, np.zeros(m.n_elems), 1.0)
+    rs = np.asarray(M.sum(1)).ravel()
+    np.testing.assert_allclose(rs[_interior(m)], (1.0 / n) ** m.dim, rtol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["tri", "tet"])
+def test_invariants_jittered(kind):
+    m = meshgen.square_tri(16, seed=3) if kind == "tri" else meshgen.cube_tet(6, seed=3)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=3)[0]
+    K, _ = _assemble(m, kappa, 0.0)
+    M, b1 = _assemble(m, np.zeros(m.n_elems), 1.0, "const", [1.0])
+    # symmetry, zero row sums (constants in the kernel of the Neumann stiffness)
+    assert abs(K - K.T).max() < 1e-15
+    np.testing.assert_allclose(np.asarray(K.sum(1)).ravel(), 0.0, atol=1e-14)
+    # total mass and total load for f = 1 equal |Omega| = 1
+    assert M.sum() == pytest.approx(1.0, rel=1e-13)
+    assert b1.sum() == pytest.approx(1.0, rel=1e-13)
+    # constant kappa: affine fields are discrete-harmonic at interior nodes, and
+    # u^T K u = |grad u|^2 |Omega|
+    K1, _ = _assemble(m, np.ones(m.n_elems), 0.0)
+    a = np.array([0.3, -1.2, 0.8][: m.dim])
+    u = a @ m.coords + 0.25
+    Ku = K1 @ u
+    np.testing.assert_allclose(Ku[_interior(m)], 0.0, atol=1e-13)
+    assert u @ Ku == pytest.approx(a @ a, rel=1e-12)
+
+
+def test_helmholtz_is_sum_of_parts():
+    m = meshgen.cube_tet(4, seed=5)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=5)[0]
+    K, _ = _assemble(m, kappa, 0.0)
+    M, _ = _assemble(m, np.zeros(m.n_elems), 1.0)
+    A, _ = _assemble(m, kappa, 1.0)
+    assert abs(A - (K + M)).max() < 1e-15
+
+
+def _fine_load(m, f):
+    """int f phi_i per node by a high-order collapsed rule on every element."""
+    d = m.dim
+    pts, w = duffy_rule(d, 8)
+    lam = np.concatenate([1 - pts.sum(1, keepdims=True), pts], 1)
+    b = np.zeros(m.n_nodes)
+    for e in range(m.n_elems):
+        v = m.conn[:, e]
+        xv = m.coords[:, v].T
+        J = (xv[1:] - xv[0]).T
+        X = xv[0] + pts @ J.T
+        fx = f(X)
+        det = abs(np.linalg.det(J))
+        for k in range(d + 1):
+            b[v[k]] += det * np.sum(w * fx * lam[:, k])
+    return b
+
+
+@pytest.mark.parametrize("kind", ["tri", "tet"])
+def test_sin_load_converges_at_third_order(kind):
+    """The sin-product load is quadrature-defined (the paper's f is an arbitrary
+    function; the rule is exact only for quadratics), so it is pinned by its distance
+    to the exact integral.  A degree-2 rule leaves an O(h^3) per-element error on
+    integrals of size O(h^d), i.e. O(h^3) relative per node: halving h must cut the error
+    by ~8.  A rule of degree 1 (wrong points) would only reach ~4, wrong weights ~1."""
+
+    def f(X):
+        return np.prod(np.sin(np.pi * X), axis=1)
+
+    errs = []
+    ns = (8, 16) if kind == "tri" else (3, 6)
+    for n in ns:
+        m = meshgen.square_tri(n, seed=1) if kind == "tri" else meshgen.cube_tet(n, seed=1)
+        _, b = _assemble(m, np.zeros(m.n_elems), 0.0, "sinprod")
+        ref = _fine_load(m, f)
+        errs.append(np.abs(b - ref).max() / np.abs(ref).max())
+        # total load -> (2/pi)^d
+        assert b.sum() == pytest.approx((2 / math.pi) ** m.dim, rel=0.1)
+    assert errs[0] < 0.05
+    assert 5.5 < errs[0] / errs[1] < 12.0
+
+
+def test_elasticity_global_invariants():
+    n = 3
+    m = meshgen.cube_tet(n, 2, seed=2)
+    rowptr, colind = oracle.pattern(10, 3, m.n_nodes, m.conn)
+    N3 = 3 * m.n_nodes
+    coef = meshgen.coefficients(m.n_elems, "elasticity", seed=2)
+    vals, rhs, _, _ = oracle.assemble_p2_elasticity(m, coef[0], coef[1], "const", [0, 0, -1.0],
+                                                    rowptr, colind)
+    K = _csr(rowptr, colind, vals, N3)
+    assert abs(K - K.T).max() < 1e-13
+    X = m.coords.T
+    for a in range(3):  # translations, every row (Neumann)
+        t = np.zeros((m.n_nodes, 3))
+        t[:, a] = 1
+        np.testing.assert_allclose(K @ t.ravel(), 0, atol=1e-13)
+    for w in np.eye(3):  # linearised rotations
+        np.testing.assert_allclose(K @ np.cross(w, X).ravel(), 0, atol=1e-13)
+    # total body force = f |Omega|
+    np.testing.assert_allclose(rhs.reshape(-1, 3).sum(0), [0, 0, -1.0], atol=1e-14)
+    # constant lam, mu: energy of a quadratic field equals its exact integral over [0,1]^3
+    ones = np.ones(m.n_elems)
+    vals1, _, _, _ = oracle.assemble_p2_elasticity(m, 1.3 * ones, 0.7 * ones, "none", None,
+                                                   rowptr, colind)
+    K1 = _csr(rowptr, colind, vals1, N3)
+    rng = np.random.default_rng(0)
+    Lm = rng.standard_normal((3, 3))
+    H = rng.standard_normal((3, 3, 3))
+    H = 0.5 * (H + H.transpose(0, 2, 1))
+    U = (X @ Lm.T + np.einsum("mi,aij,mj->ma", X, H, X)).ravel()
+    g, w = np.polynomial.legendre.leggauss(3)
+    g, w = 0.5 * (g + 1), 0.5 * w
+    P = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    W = np.prod(np.stack(np.meshgrid(w, w, w, indexing="ij"), -1).reshape(-1, 3), 1)
+    gr = Lm[None] + 2 * np.einsum("aij,mj->mai", H, P)
+    eps = 0.5 * (gr + gr.transpose(0, 2, 1))
+    dens = 1.3 * np.trace(gr, axis1=1, axis2=2) ** 2 + 2 * 0.7 * np.einsum("mij,mij->m", eps, eps)
+    assert U @ (K1 @ U) == pytest.approx(float(np.sum(W * dens)), rel=1e-11)
