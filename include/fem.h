@@ -1,0 +1,180 @@
+/*
+ * fem.h -- C ABI of the MI355X (gfx950) finite element assembly library (libfemhip.so).
+ *
+ * The library assembles the Galerkin system A x = b of Cui, Guo & Liu, "GPU
+ * Accelerated Finite Element Assembly with Runtime Compilation":
+ *   Sec. 4.1, Eq. (1)-(3): -div(kappa grad u) + c u = f on a mesh of Lagrange P1
+ *     triangles or tetrahedra, Neumann boundary (no row is modified); A_ij sums the
+ *     element integrals of every element holding nodes i and j, b_i those of every
+ *     element holding node i.
+ *   Sec. 5 (sparse variant): A is stored row-compressed; each row keeps the columns of
+ *     every node sharing an element with the row's node (the paper's gNbrNodeLen /
+ *     gNbrNodeIdx lists, here CSR rowptr / colind).  Alg. 1's scatter of element
+ *     matrices into the global matrix is done through a precomputed element-to-slot map,
+ *     either with atomic adds or colour by colour with plain read-modify-writes.
+ *   Sec. 7 (outlook: higher orders): isotropic linear elasticity on P2 tetrahedra, three
+ *     interleaved components per node (dof = 3*node + component).
+ * Beyond the paper: the adjoint (gradients of a scalar loss with respect to the
+ * per-element coefficients and the node coordinates), motivated by the PDE-constrained
+ * inverse problems of Sec. 2.
+ *
+ * Conventions for every call:
+ *   - All array arguments are DEVICE pointers on the current HIP device, owned by the
+ *     caller, unless stated otherwise.  Sizes are element counts, not bytes.
+ *   - coords: double, structure-of-arrays [dim][n_nodes].
+ *   - conn: int32, structure-of-arrays [npe][n_elems], npe = dim+1 (P1) or 10 (P2);
+ *     P2 local order: vertices 0..3, then edge nodes of edges 01 02 03 12 13 23.
+ *     Only the vertex coordinates of a P2 element are read (elements are affine).
+ *   - coef: double, structure-of-arrays [ncoef][n_elems]: kappa (Helmholtz, ncoef = 1)
+ *     or lambda, mu (elasticity, ncoef = 2).
+ *   - stream: a hipStream_t passed as void*; NULL means the null stream.  Every call
+ *     except fem_build_pattern is asynchronous on that stream; fem_build_pattern
+ *     synchronises the stream once, to learn the sizes.
+ *   - Return value: FEM_OK (0) or a negative FEM_ERR_* code.  No exception crosses the
+ *     ABI.  fem_last_error_message() gives a description of the calling thread's last
+ *     failure.  Host-side argument checks always run; device-side checks (connectivity
+ *     range, zero Jacobians) run only under FEM_VALIDATE and synchronise the stream.
+ */
+#ifndef FEM_H
+#define FEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define FEM_OK 0
+#define FEM_ERR_INVALID_ARG (-1)    /* null pointer, bad size, bad enum, bad handle */
+#define FEM_ERR_UNSUPPORTED (-2)    /* combination not provided (e.g. P2 in 2D) */
+#define FEM_ERR_OOM (-3)            /* device allocation failed */
+#define FEM_ERR_INDEX_OVERFLOW (-4) /* a count does not fit the index type */
+#define FEM_ERR_DEGENERATE (-5)     /* FEM_VALIDATE found a zero-volume element */
+#define FEM_ERR_HIP (-6)            /* a HIP runtime call failed */
+
+/* ---- forms (the weak forms of Sec. 4.1 Eq. (2) and its elasticity analogue) ---- */
+#define FEM_FORM_HELMHOLTZ 1  /* (kappa grad v, grad u) + c (v, u); P1; coef = kappa */
+#define FEM_FORM_ELASTICITY 2 /* (lam div v, div u) + (2 mu eps(v), eps(u)); P2 3D;
+                                  coef = lambda, mu */
+
+/* ---- right-hand sides (v, f) ---- */
+#define FEM_LOAD_NONE 0    /* rhs untouched (may be NULL) */
+#define FEM_LOAD_CONST 1   /* f = load_const (scalar: [0]; elasticity: body force [0..2]) */
+#define FEM_LOAD_SINPROD 2 /* f = prod_a sin(pi x_a) (Helmholtz only), by quadrature */
+
+/* ---- flags ---- */
+#define FEM_SCATTER_ATOMIC 0x0u   /* scatter with device-scope FP64 atomic adds */
+#define FEM_SCATTER_COLOURED 0x1u /* colour by colour, plain read-modify-write:
+                                     bitwise reproducible run to run */
+#define FEM_ACCUMULATE 0x2u       /* add into the outputs instead of overwriting them */
+#define FEM_VALIDATE 0x4u         /* device-side input checks (synchronises) */
+
+typedef struct fem_pattern fem_pattern; /* opaque, library-owned */
+
+typedef struct {
+    int32_t dim;   /* 2 or 3 */
+    int32_t order; /* 1, or 2 (dim 3 only) */
+    int64_t n_nodes;
+    int64_t n_elems;
+    const double *coords; /* device [dim][n_nodes] */
+    const int32_t *conn;  /* device [npe][n_elems] */
+} fem_mesh;
+
+typedef struct {
+    int32_t kind;          /* FEM_FORM_* */
+    int32_t load;          /* FEM_LOAD_* */
+    double reaction;       /* c of Eq. (1) (lambda there); Helmholtz only */
+    double load_const[3];  /* FEM_LOAD_CONST values */
+} fem_form;
+
+typedef struct {
+    int64_t n_rows;      /* n_nodes * ncomp */
+    int64_t nnz;         /* stored entries of the dof-level matrix */
+    int64_t nnz_nodes;   /* stored entries of the node-level pattern */
+    int32_t ncomp;       /* 1 (scalar) or 3 (elasticity) */
+    int32_t npe;         /* nodes per element */
+    int32_t n_colours;   /* element colours of the coloured scatter */
+    int32_t max_row;     /* longest dof-level row */
+    int64_t device_bytes; /* device memory held by the handle */
+} fem_pattern_info;
+
+/*
+ * fem_build_pattern -- FunctionSpace set-up of Sec. 4.2 / the sparse structure of
+ * Sec. 5.  From the connectivity alone it builds, on the device:
+ *   the node-level CSR pattern (rows ascending, columns ascending, diagonal included,
+ *   explicit structural zeros kept), the element-to-slot map, and a colouring of the
+ *   elements in which no two elements of one colour share a node.
+ * mesh->coords is not read.  ncomp = 1 for scalar forms, 3 for elasticity.
+ * flags: FEM_VALIDATE checks every conn entry against n_nodes.
+ * *out receives a handle owned by the library; release it with fem_pattern_destroy.
+ * Errors: INVALID_ARG (bad sizes/pointers/conn out of range under FEM_VALIDATE),
+ *   UNSUPPORTED (dim/order/ncomp combination; more than 128 colours; a row with more
+ *   than 2048 candidate entries), INDEX_OVERFLOW (nnz does not fit int32),
+ *   OOM, HIP.  Synchronises `stream` once.
+ */
+int fem_build_pattern(const fem_mesh *mesh, int32_t ncomp, unsigned flags, fem_pattern **out,
+                      void *stream);
+
+/* Sizes of a pattern (host struct, filled synchronously; no device work). */
+int fem_pattern_query(const fem_pattern *pattern, fem_pattern_info *info);
+
+/*
+ * Writes the dof-level CSR arrays: rowptr [n_rows+1] and colind [nnz], int32, device.
+ * For ncomp = 3 rows are dofs 3*node + component and each node-level column expands
+ * to three consecutive dof columns.  Asynchronous on `stream`.
+ */
+int fem_pattern_export(const fem_pattern *pattern, int32_t *rowptr, int32_t *colind,
+                       void *stream);
+
+/* Writes each element's colour (int32 [n_elems], device).  Asynchronous. */
+int fem_pattern_colours(const fem_pattern *pattern, int32_t *colour, void *stream);
+
+/* Releases a handle (NULL is ignored).  Synchronises the device first. */
+void fem_pattern_destroy(fem_pattern *pattern);
+
+/*
+ * fem_assemble -- WeakForm.build of Sec. 4.2 and Alg. 1: per element, the geometry
+ * Jacobian, the reference-basis gradients and the quadrature of the form and load,
+ * then the scatter-add of the element matrix and vector into values and rhs.
+ *   values: double [nnz] in the order of fem_pattern_export's colind.
+ *   rhs:    double [n_rows], may be NULL when form->load == FEM_LOAD_NONE.
+ * flags: FEM_SCATTER_ATOMIC or FEM_SCATTER_COLOURED, optionally FEM_ACCUMULATE
+ * (otherwise values and rhs are zero-filled first, on the stream) and FEM_VALIDATE.
+ * The mesh must have the connectivity the pattern was built from (same pointer
+ * contents and sizes); coordinates and coefficients may change between calls.
+ * Errors: INVALID_ARG, UNSUPPORTED (form/element combination), DEGENERATE
+ *   (FEM_VALIDATE only), HIP.
+ */
+int fem_assemble(const fem_pattern *pattern, const fem_mesh *mesh, const fem_form *form,
+                 const double *coef, double *values, double *rhs, unsigned flags,
+                 void *stream);
+
+/*
+ * fem_assemble_backward -- adjoint of fem_assemble for the scalar loss
+ *   L = sum_k grad_values[k] * values[k] + sum_r grad_rhs[r] * rhs[r].
+ *   grad_values [nnz] and grad_rhs [n_rows] are inputs; either may be NULL (= zero).
+ *   grad_coef [ncoef][n_elems]: dL/dcoef per element, overwritten (or added to under
+ *     FEM_ACCUMULATE); NULL = not requested.
+ *   grad_coords [dim][n_nodes]: dL/dcoords, overwritten (or added to); NULL = not
+ *     requested.  For P2 only vertex nodes receive gradient (edge-node coordinates are
+ *     not read by the forward pass).
+ * The scatter of grad_coords follows FEM_SCATTER_ATOMIC / FEM_SCATTER_COLOURED.
+ */
+int fem_assemble_backward(const fem_pattern *pattern, const fem_mesh *mesh,
+                          const fem_form *form, const double *coef,
+                          const double *grad_values, const double *grad_rhs,
+                          double *grad_coef, double *grad_coords, unsigned flags,
+                          void *stream);
+
+/* Static description of a return code. */
+const char *fem_error_string(int code);
+
+/* Description of the calling thread's most recent failure ("" if none). */
+const char *fem_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEM_H */

@@ -1,0 +1,16 @@
+"""MI355X (gfx950) finite element assembly: HIP kernels behind a C ABI (include/fem.h).
+
+Importing the package loads libfemhip.so; it raises ImportError when the library has
+not been built (python -m paper_1802_03433_amd.build).  There is no CPU fallback.
+"""
+
+from .api import (  # noqa: F401
+    FemAssemble,
+    Form,
+    Mesh,
+    Pattern,
+    assemble,
+    assemble_backward,
+    fem_assemble,
+)
+from ._lib import FemError  # noqa: F401

@@ -1,0 +1,120 @@
+"""ctypes binding of libfemhip.so (the C ABI declared in include/fem.h).
+
+Argument marshalling only: every step of assembly runs in the library's HIP kernels.
+Torch tensors supply device memory and the current stream.  If the library is missing
+this module raises at import time; there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfemhip.so")
+
+FEM_OK = 0
+ERRORS = {
+    -1: "FEM_ERR_INVALID_ARG",
+    -2: "FEM_ERR_UNSUPPORTED",
+    -3: "FEM_ERR_OOM",
+    -4: "FEM_ERR_INDEX_OVERFLOW",
+    -5: "FEM_ERR_DEGENERATE",
+    -6: "FEM_ERR_HIP",
+}
+FORM_HELMHOLTZ = 1
+FORM_ELASTICITY = 2
+LOAD = {"none": 0, "const": 1, "sinprod": 2}
+SCATTER_ATOMIC = 0x0
+SCATTER_COLOURED = 0x1
+ACCUMULATE = 0x2
+VALIDATE = 0x4
+
+# Every extern "C" function of include/fem.h (checked by the tests).
+EXPORTS = (
+    "fem_build_pattern",
+    "fem_pattern_query",
+    "fem_pattern_export",
+    "fem_pattern_colours",
+    "fem_pattern_destroy",
+    "fem_assemble",
+    "fem_assemble_backward",
+    "fem_error_string",
+    "fem_last_error_message",
+)
+
+
+class FemError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        self.code = code
+        super().__init__(f"{where}: {ERRORS.get(code, code)}: {msg}")
+
+
+class fem_mesh(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("n_nodes", ctypes.c_int64),
+        ("n_elems", ctypes.c_int64),
+        ("coords", ctypes.c_void_p),
+        ("conn", ctypes.c_void_p),
+    ]
+
+
+class fem_form(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("load", ctypes.c_int32),
+        ("reaction", ctypes.c_double),
+        ("load_const", ctypes.c_double * 3),
+    ]
+
+
+class fem_pattern_info(ctypes.Structure):
+    _fields_ = [
+        ("n_rows", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("nnz_nodes", ctypes.c_int64),
+        ("ncomp", ctypes.c_int32),
+        ("npe", ctypes.c_int32),
+        ("n_colours", ctypes.c_int32),
+        ("max_row", ctypes.c_int32),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"libfemhip.so not found at {path}; build it with "
+            "`python -m paper_1802_03433_amd.build` (hipcc, gfx950)"
+        )
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    pm = ctypes.POINTER(fem_mesh)
+    pf = ctypes.POINTER(fem_form)
+    L.fem_build_pattern.argtypes = [pm, ctypes.c_int32, ctypes.c_uint, ctypes.POINTER(P), P]
+    L.fem_pattern_query.argtypes = [P, ctypes.POINTER(fem_pattern_info)]
+    L.fem_pattern_export.argtypes = [P, P, P, P]
+    L.fem_pattern_colours.argtypes = [P, P, P]
+    L.fem_pattern_destroy.argtypes = [P]
+    L.fem_pattern_destroy.restype = None
+    L.fem_assemble.argtypes = [P, pm, pf, P, P, P, ctypes.c_uint, P]
+    L.fem_assemble_backward.argtypes = [P, pm, pf, P, P, P, P, P, ctypes.c_uint, P]
+    L.fem_error_string.argtypes = [ctypes.c_int]
+    L.fem_error_string.restype = ctypes.c_char_p
+    L.fem_last_error_message.argtypes = []
+    L.fem_last_error_message.restype = ctypes.c_char_p
+    for n in ("fem_build_pattern", "fem_pattern_query", "fem_pattern_export",
+              "fem_pattern_colours", "fem_assemble", "fem_assemble_backward"):
+        getattr(L, n).restype = ctypes.c_int
+    return L
+
+
+lib = load_library()
+
+
+def check(rc: int, where: str) -> None:
+    if rc != FEM_OK:
+        msg = lib.fem_last_error_message().decode()
+        raise FemError(rc, where, msg)

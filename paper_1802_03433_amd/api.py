@@ -1,0 +1,233 @@
+"""Python front end of libfemhip: pattern handles, assembly, adjoint, autograd.
+
+Mirrors the C ABI one to one (fem_build_pattern -> Pattern, fem_assemble -> assemble,
+fem_assemble_backward -> assemble_backward).  Tensors must already live on the GPU;
+nothing here computes any part of the method.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib as L
+
+_SCATTER = {"atomic": L.SCATTER_ATOMIC, "coloured": L.SCATTER_COLOURED}
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _flags(scatter: str, accumulate: bool, validate: bool) -> int:
+    if scatter not in _SCATTER:
+        raise ValueError(f"scatter must be one of {list(_SCATTER)}")
+    f = _SCATTER[scatter]
+    if accumulate:
+        f |= L.ACCUMULATE
+    if validate:
+        f |= L.VALIDATE
+    return f
+
+
+class Mesh:
+    """Device mesh: coords float64 [dim][n_nodes], conn int32 [npe][n_elems]."""
+
+    def __init__(self, coords: torch.Tensor, conn: torch.Tensor, order: int = 1):
+        _need(coords, torch.float64, "coords")
+        _need(conn, torch.int32, "conn")
+        self.coords = coords
+        self.conn = conn
+        self.dim = int(coords.shape[0])
+        self.order = int(order)
+        self.n_nodes = int(coords.shape[1])
+        self.n_elems = int(conn.shape[1])
+
+    def with_coords(self, coords: torch.Tensor) -> "Mesh":
+        return Mesh(coords, self.conn, self.order)
+
+    def cstruct(self) -> L.fem_mesh:
+        m = L.fem_mesh()
+        m.dim = self.dim
+        m.order = self.order
+        m.n_nodes = self.n_nodes
+        m.n_elems = self.n_elems
+        m.coords = self.coords.data_ptr()
+        m.conn = self.conn.data_ptr()
+        return m
+
+
+@dataclass
+class Form:
+    """kind: "helmholtz" or "elasticity"; load: "none" | "const" | "sinprod"."""
+
+    kind: str = "helmholtz"
+    load: str = "none"
+    reaction: float = 1.0
+    load_const: tuple = field(default=(0.0, 0.0, 0.0))
+
+    def cstruct(self) -> L.fem_form:
+        f = L.fem_form()
+        f.kind = {"helmholtz": L.FORM_HELMHOLTZ, "elasticity": L.FORM_ELASTICITY}[self.kind]
+        f.load = L.LOAD[self.load]
+        f.reaction = float(self.reaction)
+        lc = list(self.load_const) + [0.0] * (3 - len(self.load_const))
+        for i in range(3):
+            f.load_const[i] = float(lc[i])
+        return f
+
+    @property
+    def ncomp(self) -> int:
+        return 3 if self.kind == "elasticity" else 1
+
+
+class Pattern:
+    """Owning wrapper of a fem_pattern handle (sparsity, slot map, colouring)."""
+
+    def __init__(self, mesh: Mesh, ncomp: int = 1, validate: bool = False):
+        self.mesh = mesh
+        self._h = ctypes.c_void_p()
+        ms = mesh.cstruct()
+        flags = L.VALIDATE if validate else 0
+        rc = L.lib.fem_build_pattern(ctypes.byref(ms), int(ncomp), flags, ctypes.byref(self._h),
+                                     _stream_ptr(mesh.coords.device))
+        L.check(rc, "fem_build_pattern")
+        info = L.fem_pattern_info()
+        L.check(L.lib.fem_pattern_query(self._h, ctypes.byref(info)), "fem_pattern_query")
+        self.n_rows = int(info.n_rows)
+        self.nnz = int(info.nnz)
+        self.nnz_nodes = int(info.nnz_nodes)
+        self.ncomp = int(info.ncomp)
+        self.npe = int(info.npe)
+        self.n_colours = int(info.n_colours)
+        self.max_row = int(info.max_row)
+        self.device_bytes = int(info.device_bytes)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise ValueError("pattern has been closed")
+        return self._h
+
+    def export(self):
+        dev = self.mesh.coords.device
+        rowptr = torch.empty(self.n_rows + 1, dtype=torch.int32, device=dev)
+        colind = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+        L.check(L.lib.fem_pattern_export(self.handle, _ptr(rowptr), _ptr(colind), _stream_ptr(dev)),
+                "fem_pattern_export")
+        return rowptr, colind
+
+    def colours(self):
+        dev = self.mesh.coords.device
+        c = torch.empty(self.mesh.n_elems, dtype=torch.int32, device=dev)
+        L.check(L.lib.fem_pattern_colours(self.handle, _ptr(c), _stream_ptr(dev)),
+                "fem_pattern_colours")
+        return c
+
+    def close(self):
+        if self._h:
+            L.lib.fem_pattern_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def assemble(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tensor,
+             values: torch.Tensor | None = None, rhs: torch.Tensor | None = None,
+             scatter: str = "atomic", accumulate: bool = False, validate: bool = False):
+    """fem_assemble; returns (values [nnz], rhs [n_rows] or None)."""
+    _need(coef, torch.float64, "coef")
+    dev = mesh.coords.device
+    if values is None:
+        values = torch.empty(pattern.nnz, dtype=torch.float64, device=dev)
+    if rhs is None and form.load != "none":
+        rhs = torch.empty(pattern.n_rows, dtype=torch.float64, device=dev)
+    _need(values, torch.float64, "values")
+    if rhs is not None:
+        _need(rhs, torch.float64, "rhs")
+    ms, fs = mesh.cstruct(), form.cstruct()
+    rc = L.lib.fem_assemble(pattern.handle, ctypes.byref(ms), ctypes.byref(fs), _ptr(coef),
+                            _ptr(values), _ptr(rhs), _flags(scatter, accumulate, validate),
+                            _stream_ptr(dev))
+    L.check(rc, "fem_assemble")
+    return values, rhs
+
+
+def assemble_backward(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tensor,
+                      grad_values: torch.Tensor | None, grad_rhs: torch.Tensor | None,
+                      want_coef: bool = True, want_coords: bool = True,
+                      scatter: str = "atomic", accumulate: bool = False,
+                      grad_coef: torch.Tensor | None = None,
+                      grad_coords: torch.Tensor | None = None):
+    """fem_assemble_backward; returns (grad_coef [ncoef][E] or None, grad_coords or None)."""
+    _need(coef, torch.float64, "coef")
+    dev = mesh.coords.device
+    for t, n in ((grad_values, "grad_values"), (grad_rhs, "grad_rhs")):
+        if t is not None:
+            _need(t, torch.float64, n)
+    if want_coef and grad_coef is None:
+        grad_coef = torch.empty_like(coef)
+    if want_coords and grad_coords is None:
+        grad_coords = torch.empty_like(mesh.coords)
+    ms, fs = mesh.cstruct(), form.cstruct()
+    rc = L.lib.fem_assemble_backward(pattern.handle, ctypes.byref(ms), ctypes.byref(fs),
+                                     _ptr(coef), _ptr(grad_values), _ptr(grad_rhs),
+                                     _ptr(grad_coef if want_coef else None),
+                                     _ptr(grad_coords if want_coords else None),
+                                     _flags(scatter, accumulate, False), _stream_ptr(dev))
+    L.check(rc, "fem_assemble_backward")
+    return (grad_coef if want_coef else None), (grad_coords if want_coords else None)
+
+
+class FemAssemble(torch.autograd.Function):
+    """(coords, coef) -> (values, rhs) with the hand-written adjoint kernels as backward.
+    The pattern, connectivity and form are non-tensor context; only the inputs are
+    saved and the geometry is recomputed in the backward kernel."""
+
+    @staticmethod
+    def forward(ctx, coords, coef, pattern, mesh, form, scatter):
+        m = mesh.with_coords(coords.contiguous())
+        values, rhs = assemble(pattern, m, form, coef.contiguous(), scatter=scatter)
+        if rhs is None:
+            rhs = torch.zeros(pattern.n_rows, dtype=torch.float64, device=coords.device)
+        ctx.save_for_backward(coords, coef)
+        ctx.pattern, ctx.mesh, ctx.form, ctx.scatter = pattern, mesh, form, scatter
+        return values, rhs
+
+    @staticmethod
+    def backward(ctx, gvalues, grhs):
+        coords, coef = ctx.saved_tensors
+        m = ctx.mesh.with_coords(coords.contiguous())
+        gv = None if gvalues is None else gvalues.contiguous()
+        gr = None if grhs is None else grhs.contiguous()
+        gcoef, gcoords = assemble_backward(
+            ctx.pattern, m, ctx.form, coef.contiguous(), gv, gr,
+            want_coef=ctx.needs_input_grad[1], want_coords=ctx.needs_input_grad[0],
+            scatter=ctx.scatter)
+        return gcoords, gcoef, None, None, None, None
+
+
+def fem_assemble(coords, coef, pattern: Pattern, mesh: Mesh, form: Form, scatter: str = "atomic"):
+    """Differentiable assembly: returns (values, rhs)."""
+    return FemAssemble.apply(coords, coef, pattern, mesh, form, scatter)

@@ -1,0 +1,247 @@
+// C ABI entry points: argument checks, dispatch to the kernels, error reporting.
+#include "fem_internal.h"
+
+namespace fem {
+const char *last_error();
+}
+
+using namespace fem;
+
+namespace {
+
+int npe_of(int dim, int order)
+{
+    if (order == 1) return dim + 1;
+    if (order == 2 && dim == 3) return 10;
+    return -1;
+}
+
+int check_mesh(const fem_mesh *m, bool need_coords)
+{
+    if (!m) return fail(FEM_ERR_INVALID_ARG, "mesh is NULL");
+    if (m->dim != 2 && m->dim != 3) return fail(FEM_ERR_INVALID_ARG, "dim must be 2 or 3");
+    if (m->order != 1 && m->order != 2) return fail(FEM_ERR_INVALID_ARG, "order must be 1 or 2");
+    if (npe_of(m->dim, m->order) < 0)
+        return fail(FEM_ERR_UNSUPPORTED, "P2 elements are provided in 3D only");
+    if (m->n_nodes < 0 || m->n_elems < 0)
+        return fail(FEM_ERR_INVALID_ARG, "negative mesh size");
+    if (m->n_elems > 0 && !m->conn) return fail(FEM_ERR_INVALID_ARG, "conn is NULL");
+    if (need_coords && m->n_elems > 0 && !m->coords)
+        return fail(FEM_ERR_INVALID_ARG, "coords is NULL");
+    return FEM_OK;
+}
+
+int check_same_mesh(const fem_pattern *p, const fem_mesh *m)
+{
+    if (!p) return fail(FEM_ERR_INVALID_ARG, "pattern is NULL");
+    if (p->dim != m->dim || p->order != m->order || p->n_nodes != m->n_nodes ||
+        p->n_elems != m->n_elems)
+        return fail(FEM_ERR_INVALID_ARG, "mesh does not match the pattern it was built for");
+    return FEM_OK;
+}
+
+int check_form(const fem_pattern *p, const fem_form *f)
+{
+    if (!f) return fail(FEM_ERR_INVALID_ARG, "form is NULL");
+    if (f->load != FEM_LOAD_NONE && f->load != FEM_LOAD_CONST && f->load != FEM_LOAD_SINPROD)
+        return fail(FEM_ERR_INVALID_ARG, "unknown load kind");
+    if (f->kind == FEM_FORM_HELMHOLTZ) {
+        if (p->order != 1 || p->ncomp != 1)
+            return fail(FEM_ERR_UNSUPPORTED, "Helmholtz form is provided for scalar P1 meshes");
+        return FEM_OK;
+    }
+    if (f->kind == FEM_FORM_ELASTICITY) {
+        if (p->order != 2 || p->dim != 3 || p->ncomp != 3)
+            return fail(FEM_ERR_UNSUPPORTED,
+                        "elasticity is provided for P2 tetrahedra with a 3-component pattern");
+        if (f->load == FEM_LOAD_SINPROD)
+            return fail(FEM_ERR_UNSUPPORTED, "elasticity takes no sin-product load");
+        return fail(FEM_ERR_UNSUPPORTED, "elasticity kernel not available in this build");
+    }
+    return fail(FEM_ERR_INVALID_ARG, "unknown form kind");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fem_error_string(int code)
+{
+    switch (code) {
+    case FEM_OK: return "ok";
+    case FEM_ERR_INVALID_ARG: return "invalid argument";
+    case FEM_ERR_UNSUPPORTED: return "unsupported combination";
+    case FEM_ERR_OOM: return "out of device memory";
+    case FEM_ERR_INDEX_OVERFLOW: return "index overflow";
+    case FEM_ERR_DEGENERATE: return "degenerate element";
+    case FEM_ERR_HIP: return "HIP runtime error";
+    default: return "unknown error code";
+    }
+}
+
+const char *fem_last_error_message(void) { return fem::last_error(); }
+
+int fem_build_pattern(const fem_mesh *mesh, int32_t ncomp, unsigned flags, fem_pattern **out,
+                      void *stream)
+{
+    clear_error();
+    if (!out) return fail(FEM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    FEM_TRY(check_mesh(mesh, false));
+    if (ncomp != 1 && ncomp != 3) return fail(FEM_ERR_INVALID_ARG, "ncomp must be 1 or 3");
+    if (ncomp == 3 && mesh->dim != 3)
+        return fail(FEM_ERR_UNSUPPORTED, "vector patterns are provided in 3D");
+    if (mesh->n_nodes == 0) return fail(FEM_ERR_INVALID_ARG, "mesh has no nodes");
+    const int npe = npe_of(mesh->dim, mesh->order);
+    if (mesh->n_nodes * ncomp > INT32_MAX || mesh->n_elems * npe * npe > INT32_MAX)
+        return fail(FEM_ERR_INDEX_OVERFLOW, "mesh too large for int32 indices");
+    auto *p = new (std::nothrow) fem_pattern();
+    if (!p) return fail(FEM_ERR_OOM, "host allocation failed");
+    FEM_HIP_TRY(hipGetDevice(&p->device));
+    p->dim = mesh->dim;
+    p->order = mesh->order;
+    p->npe = npe;
+    p->ncomp = ncomp;
+    p->n_nodes = mesh->n_nodes;
+    p->n_elems = mesh->n_elems;
+    p->n_rows = mesh->n_nodes * ncomp;
+    int rc = build_pattern_device(p, mesh, flags, (hipStream_t)stream);
+    if (rc != FEM_OK) {
+        std::string msg = fem::last_error();
+        fem_pattern_destroy(p);
+        set_error(msg);
+        return rc;
+    }
+    *out = p;
+    return FEM_OK;
+}
+
+int fem_pattern_query(const fem_pattern *p, fem_pattern_info *info)
+{
+    clear_error();
+    if (!p || !info) return fail(FEM_ERR_INVALID_ARG, "NULL argument");
+    info->n_rows = p->n_rows;
+    info->nnz = p->nnz;
+    info->nnz_nodes = p->nnz_nodes;
+    info->ncomp = p->ncomp;
+    info->npe = p->npe;
+    info->n_colours = p->n_colours;
+    info->max_row = p->max_row;
+    info->device_bytes = p->device_bytes;
+    return FEM_OK;
+}
+
+namespace {
+// dof-level export: row 3n+a of a 3-component pattern holds, for every node column m of
+// node row n, the dof columns 3m, 3m+1, 3m+2.
+__global__ void k_export_rowptr(const int32_t *__restrict__ rp, int64_t N, int nc,
+                                int32_t *__restrict__ out)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t R = N * nc;
+    if (r > R) return;
+    if (r == R) {
+        out[r] = rp[N] * nc * nc;
+        return;
+    }
+    int64_t n = r / nc, a = r - n * nc;
+    int32_t len = rp[n + 1] - rp[n];
+    out[r] = (int32_t)(rp[n] * nc * nc + a * len * nc);
+}
+
+__global__ void k_export_colind(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                int64_t N, int nc, int32_t *__restrict__ out)
+{
+    int64_t n = blockIdx.x;
+    int32_t beg = rp[n], len = rp[n + 1] - rp[n];
+    for (int32_t k = threadIdx.x; k < len * nc * nc; k += blockDim.x) {
+        int32_t a = k / (len * nc);
+        int32_t rem = k - a * len * nc;
+        int32_t t = rem / nc, b = rem - t * nc;
+        out[(int64_t)beg * nc * nc + k] = ci[beg + t] * nc + b;
+    }
+    (void)N;
+}
+}  // namespace
+
+int fem_pattern_export(const fem_pattern *p, int32_t *rowptr, int32_t *colind, void *stream)
+{
+    clear_error();
+    if (!p) return fail(FEM_ERR_INVALID_ARG, "pattern is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (rowptr) {
+        int64_t n = p->n_rows + 1;
+        hipLaunchKernelGGL(k_export_rowptr, dim3(grid_for(n, 256)), dim3(256), 0, s, p->rowptr_n,
+                           p->n_nodes, p->ncomp, rowptr);
+    }
+    if (colind && p->n_nodes > 0)
+        hipLaunchKernelGGL(k_export_colind, dim3((unsigned)p->n_nodes), dim3(64), 0, s, p->rowptr_n,
+                           p->colind_n, p->n_nodes, p->ncomp, colind);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+int fem_pattern_colours(const fem_pattern *p, int32_t *colour, void *stream)
+{
+    clear_error();
+    if (!p || (!colour && p->n_elems > 0)) return fail(FEM_ERR_INVALID_ARG, "NULL argument");
+    if (p->n_elems > 0)
+        FEM_HIP_TRY(hipMemcpyAsync(colour, p->colour, sizeof(int32_t) * p->n_elems,
+                                   hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return FEM_OK;
+}
+
+void fem_pattern_destroy(fem_pattern *p)
+{
+    if (!p) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    for (auto &b : p->owned) (void)hipFree(b.ptr);
+    (void)hipSetDevice(cur);
+    delete p;
+}
+
+int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *form,
+                 const double *coef, double *values, double *rhs, unsigned flags, void *stream)
+{
+    clear_error();
+    FEM_TRY(check_mesh(mesh, true));
+    FEM_TRY(check_same_mesh(p, mesh));
+    FEM_TRY(check_form(p, form));
+    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE))
+        return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
+    if (!values && p->nnz > 0) return fail(FEM_ERR_INVALID_ARG, "values is NULL");
+    if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
+    if (form->load != FEM_LOAD_NONE && !rhs && p->n_rows > 0)
+        return fail(FEM_ERR_INVALID_ARG, "rhs is NULL but the form has a load");
+    hipStream_t s = (hipStream_t)stream;
+    if (!(flags & FEM_ACCUMULATE)) {
+        FEM_TRY(fill_zero_f64(values, p->nnz, s));
+        if (rhs) FEM_TRY(fill_zero_f64(rhs, p->n_rows, s));
+    }
+    const double *rhs_ok = (form->load == FEM_LOAD_NONE) ? nullptr : rhs;
+    return p1_forward(p, mesh, form, coef, values, const_cast<double *>(rhs_ok), flags, s);
+}
+
+int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_form *form,
+                          const double *coef, const double *grad_values, const double *grad_rhs,
+                          double *grad_coef, double *grad_coords, unsigned flags, void *stream)
+{
+    clear_error();
+    FEM_TRY(check_mesh(mesh, true));
+    FEM_TRY(check_same_mesh(p, mesh));
+    FEM_TRY(check_form(p, form));
+    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE))
+        return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
+    if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (!(flags & FEM_ACCUMULATE) && grad_coords)
+        FEM_TRY(fill_zero_f64(grad_coords, p->dim * p->n_nodes, s));
+    if (!grad_coef && !grad_coords) return FEM_OK;
+    const double *grhs = (form->load == FEM_LOAD_NONE) ? nullptr : grad_rhs;
+    return p1_backward(p, mesh, form, coef, grad_values, grhs, grad_coef, grad_coords, flags, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+// Error state, device scans and fills shared by the library's kernels.
+#include "fem_internal.h"
+
+namespace fem {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+const char *last_error() { return g_last_error.c_str(); }
+
+int pattern_alloc(fem_pattern *p, void **ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(e == hipErrorOutOfMemory ? FEM_ERR_OOM : FEM_ERR_HIP,
+                    std::string("hipMalloc(") + std::to_string(bytes) +
+                        "): " + hipGetErrorString(e));
+    }
+    p->owned.push_back(DevBuf{*ptr, bytes});
+    p->device_bytes += (int64_t)bytes;
+    return FEM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// fill
+// ---------------------------------------------------------------------------------------
+__global__ void k_fill_zero_f64(double *__restrict__ p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // two doubles per thread per step, 16-byte stores where aligned
+    for (; 2 * i + 1 < n; i += stride) {
+        reinterpret_cast<double2 *>(p)[i] = make_double2(0.0, 0.0);
+    }
+    if (2 * i < n && 2 * i + 1 >= n) p[2 * i] = 0.0;
+}
+
+int fill_zero_f64(double *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return FEM_OK;
+    if (((uintptr_t)p & 15) != 0) {
+        // unaligned start: fall back to the element-wise path of the same kernel layout
+        hipLaunchKernelGGL(k_fill_zero_f64, dim3(1), dim3(1), 0, s, p, (int64_t)1);
+        return fill_zero_f64(p + 1, n - 1, s);
+    }
+    int64_t pairs = (n + 1) / 2;
+    int threads = 256;
+    int64_t blocks = (pairs + threads - 1) / threads;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_zero_f64, dim3((unsigned)blocks), dim3(threads), 0, s, p, n);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// exclusive scan of int32 counts -> int64 offsets (three passes: tile sums, scan of the
+// tile sums by one workgroup, tile-local scans plus the tile offset)
+// ---------------------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t *total)
+{
+    // Hillis-Steele over the workgroup in LDS
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int64_t add = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int64_t incl = sh[t];
+    *total = sh[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t *__restrict__ in,
+                                                             int64_t n, int64_t *__restrict__ sums)
+{
+    __shared__ int64_t sh[kScanThreads];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t acc = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+        if (i < n) acc += in[i];
+    }
+    int64_t total;
+    block_exclusive_scan(acc, sh, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int64_t *__restrict__ sums,
+                                                             int64_t m)
+{
+    __shared__ int64_t sh[kScanThreads];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < m; base += kScanThreads) {
+        int64_t i = base + threadIdx.x;
+        int64_t v = (i < m) ? sums[i] : 0;
+        int64_t total;
+        int64_t ex = block_exclusive_scan(v, sh, &total);
+        if (i < m) sums[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) sums[m] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t *__restrict__ in,
+                                                             int64_t n,
+                                                             const int64_t *__restrict__ sums,
+                                                             int64_t *__restrict__ out)
+{
+    __shared__ int64_t sh[kScanThreads];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t vals[kScanItems];
+    int64_t acc = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        vals[k] = (i < n) ? in[i] : 0;
+        acc += vals[k];
+    }
+    int64_t total;
+    int64_t ex = block_exclusive_scan(acc, sh, &total) + sums[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = ex;
+        ex += vals[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = sums[gridDim.x];
+}
+
+int scan_counts_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s)
+{
+    int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles == 0) {
+        FEM_HIP_TRY(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+        return FEM_OK;
+    }
+    int64_t *sums = nullptr;
+    FEM_HIP_TRY(hipMallocAsync((void **)&sums, sizeof(int64_t) * (tiles + 1), s));
+    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, sums, tiles);
+    hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n, sums,
+                       out);
+    hipError_t e = hipGetLastError();
+    hipFreeAsync(sums, s);
+    if (e != hipSuccess) return fail(FEM_ERR_HIP, std::string("scan: ") + hipGetErrorString(e));
+    return FEM_OK;
+}
+
+}  // namespace fem

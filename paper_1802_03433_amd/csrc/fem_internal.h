@@ -1,0 +1,131 @@
+// Internal declarations of the HIP assembly library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fem.h"
+
+namespace fem {
+
+// ---------------------------------------------------------------------------------------
+// error state
+// ---------------------------------------------------------------------------------------
+void set_error(const std::string &msg);
+void clear_error();
+
+struct Status {
+    int code = FEM_OK;
+};
+
+#define FEM_HIP_TRY(expr)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::fem::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));       \
+            return e_ == hipErrorOutOfMemory ? FEM_ERR_OOM : FEM_ERR_HIP;              \
+        }                                                                              \
+    } while (0)
+
+#define FEM_TRY(expr)                    \
+    do {                                 \
+        int rc_ = (expr);                \
+        if (rc_ != FEM_OK) return rc_;   \
+    } while (0)
+
+inline int fail(int code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+// ---------------------------------------------------------------------------------------
+// device memory owned by a pattern handle
+// ---------------------------------------------------------------------------------------
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// Colour limit of the first-fit colouring (two 64-bit masks per element).
+constexpr int kMaxColours = 128;
+// Largest candidate list (sum of npe over a node's elements) a pattern row may have.
+constexpr int kRowCap = 2048;
+
+}  // namespace fem
+
+struct fem_pattern {
+    int device = 0;
+    int dim = 0, order = 0, npe = 0, ncomp = 1;
+    int64_t n_nodes = 0, n_elems = 0;
+    int64_t n_rows = 0, nnz = 0, nnz_nodes = 0;
+    int32_t max_row = 0;
+    // node-level CSR
+    int32_t *rowptr_n = nullptr;  // [n_nodes+1]
+    int32_t *colind_n = nullptr;  // [nnz_nodes]
+    // node -> element incidence
+    int32_t *n2e_ptr = nullptr;   // [n_nodes+1]
+    int32_t *n2e = nullptr;       // [n_elems*npe]
+    // element-to-slot map, node level: slot[(i*npe+j)*E + e] = index of (conn_i, conn_j)
+    // in colind_n
+    int32_t *slot = nullptr;
+    // colouring
+    int32_t n_colours = 0;
+    std::vector<int64_t> colour_ptr;  // host [n_colours+1]: colour c = perm[ptr[c]..ptr[c+1])
+    int32_t *colour = nullptr;        // [E]
+    int32_t *perm = nullptr;          // [E] elements sorted by colour, ascending within one
+    int32_t *conn_perm = nullptr;     // [npe][E] conn in perm order
+    int32_t *slot_perm = nullptr;     // [npe*npe][E] slot map in perm order
+    std::vector<fem::DevBuf> owned;
+    int64_t device_bytes = 0;
+};
+
+namespace fem {
+
+// allocation owned by a pattern
+int pattern_alloc(fem_pattern *p, void **ptr, size_t bytes);
+
+// exclusive scan of n int32 counts into out[0..n] (out[n] = total), int64 accumulation
+int scan_counts_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+
+// fill kernel (graph-capture safe alternative to hipMemsetAsync)
+int fill_zero_f64(double *p, int64_t n, hipStream_t s);
+
+// pattern construction (pattern.hip)
+int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipStream_t s);
+
+// assembly launchers (p1.hip)
+int p1_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,
+               double *values, double *rhs, unsigned flags, hipStream_t s);
+int p1_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,
+                const double *gvalues, const double *grhs, double *gcoef, double *gcoords,
+                unsigned flags, hipStream_t s);
+
+// launch geometry helper: grid of `blocks`, XCD-aware remap done inside kernels
+inline unsigned grid_for(int64_t n, int threads)
+{
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace fem
+
+// ---------------------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------------------
+namespace fem {
+
+// The hardware dispatches consecutive workgroups round-robin over the 8 XCDs, each with
+// its own L2.  Remap so that XCD x processes one contiguous range of logical blocks:
+// neighbouring elements (which share nodes, hence matrix rows) then go through one L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks)
+{
+    constexpr int kXcd = 8;
+    int64_t q = nblocks / kXcd, r = nblocks % kXcd;
+    int64_t x = b % kXcd, k = b / kXcd;
+    return x * q + (x < r ? x : r) + k;
+}
+
+}  // namespace fem

@@ -1,0 +1,471 @@
+// Sparsity pattern, element-to-slot map and element colouring, all built on the device.
+//
+// The stored matrix of the paper's sparse variant (Sec. 5) keeps, per row, the nodes
+// that share an element with the row's node.  Here:
+//   1. node -> element incidence (counting sort of the connectivity),
+//   2. per row: gather the nodes of the row's elements into LDS, bitonic-sort, count the
+//      distinct ones; scan the counts into rowptr; repeat the gather to write colind,
+//   3. slot map: for every element and local pair (i, j), the position of conn_j in the
+//      row of conn_i (binary search), stored structure-of-arrays so the assembly reads
+//      it coalesced,
+//   4. colouring: Jones-Plassmann with first-fit colours on the graph "elements sharing
+//      a vertex"; deterministic (hashed priorities, double-buffered rounds),
+//   5. elements stably sorted by colour, and colour-ordered copies of conn and slots so
+//      the coloured scatter also reads its element data coalesced.
+#include "fem_internal.h"
+
+namespace fem {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRowThreads = 64;  // one wavefront per pattern row
+
+enum : int { kErrConnRange = 1, kErrRowCap = 2, kErrSlotMissing = 4, kErrColours = 8 };
+
+__global__ void k_count_incidence(const int32_t *__restrict__ conn, int64_t E, int npe,
+                                  int64_t n_nodes, int32_t *__restrict__ deg, int *err)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E * npe) return;
+    int32_t v = conn[t];
+    if (v < 0 || v >= n_nodes) {
+        atomicOr(err, kErrConnRange);
+        return;
+    }
+    atomicAdd(&deg[v], 1);
+}
+
+__global__ void k_i64_to_i32(const int64_t *__restrict__ in, int32_t *__restrict__ out, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (int32_t)in[t];
+}
+
+__global__ void k_fill_n2e(const int32_t *__restrict__ conn, int64_t E, int npe,
+                           const int32_t *__restrict__ n2e_ptr, int32_t *__restrict__ cursor,
+                           int32_t *__restrict__ n2e)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E * npe) return;
+    int32_t v = conn[t];
+    int32_t e = (int32_t)(t % E);
+    int32_t pos = atomicAdd(&cursor[v], 1);
+    n2e[n2e_ptr[v] + pos] = e;
+}
+
+// Gathers the candidate columns of row `node` into sh[0..P) (P = next power of two of the
+// candidate count, padded with INT32_MAX) and sorts them ascending.  Returns P, or -1 when
+// the row exceeds kRowCap candidates.
+__device__ int gather_sort_row(int64_t node, const int32_t *__restrict__ n2e_ptr,
+                               const int32_t *__restrict__ n2e, const int32_t *__restrict__ conn,
+                               int64_t E, int npe, int32_t *sh)
+{
+    int beg = n2e_ptr[node], end = n2e_ptr[node + 1];
+    int cnt = (end - beg) * npe;
+    if (cnt > kRowCap) return -1;
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += kRowThreads) {
+        int32_t v = INT32_MAX;
+        if (i < cnt) {
+            int t = i / npe, k = i - t * npe;
+            v = conn[(int64_t)k * E + n2e[beg + t]];
+        }
+        sh[i] = v;
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += kRowThreads) {
+                int l = i ^ j;
+                if (l > i) {
+                    int32_t a = sh[i], b = sh[l];
+                    bool ascending = (i & k) == 0;
+                    if ((a > b) == ascending) {
+                        sh[i] = b;
+                        sh[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return P;
+}
+
+__device__ __forceinline__ bool is_head(const int32_t *sh, int i, int P)
+{
+    return i < P && sh[i] != INT32_MAX && (i == 0 || sh[i] != sh[i - 1]);
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_row_count(const int32_t *__restrict__ n2e_ptr,
+                                                           const int32_t *__restrict__ n2e,
+                                                           const int32_t *__restrict__ conn,
+                                                           int64_t E, int npe,
+                                                           int32_t *__restrict__ rowlen, int *err)
+{
+    __shared__ int32_t sh[kRowCap];
+    int64_t node = blockIdx.x;
+    int P = gather_sort_row(node, n2e_ptr, n2e, conn, E, npe, sh);
+    if (P < 0) {
+        if (threadIdx.x == 0) {
+            atomicOr(err, kErrRowCap);
+            rowlen[node] = 0;
+        }
+        return;
+    }
+    int u = 0;
+    for (int base = 0; base < P; base += kRowThreads) {
+        bool h = is_head(sh, base + threadIdx.x, P);
+        u += __popcll(__ballot(h));
+    }
+    if (threadIdx.x == 0) rowlen[node] = u;
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_row_fill(const int32_t *__restrict__ n2e_ptr,
+                                                          const int32_t *__restrict__ n2e,
+                                                          const int32_t *__restrict__ conn,
+                                                          int64_t E, int npe,
+                                                          const int32_t *__restrict__ rowptr,
+                                                          int32_t *__restrict__ colind)
+{
+    __shared__ int32_t sh[kRowCap];
+    int64_t node = blockIdx.x;
+    int P = gather_sort_row(node, n2e_ptr, n2e, conn, E, npe, sh);
+    if (P < 0) return;
+    int out = rowptr[node];
+    for (int base = 0; base < P; base += kRowThreads) {
+        int i = base + threadIdx.x;
+        bool h = is_head(sh, i, P);
+        uint64_t m = __ballot(h);
+        if (h) colind[out + lanes_below(m)] = sh[i];
+        out += __popcll(m);
+    }
+}
+
+__global__ void k_slot_map(const int32_t *__restrict__ conn, int64_t E, int npe,
+                           const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+                           int32_t *__restrict__ slot, int *err)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E * npe) return;
+    int i = (int)(t / E);
+    int64_t e = t - (int64_t)i * E;
+    int32_t row = conn[(int64_t)i * E + e];
+    int32_t lo0 = rowptr[row], hi0 = rowptr[row + 1];
+    for (int j = 0; j < npe; ++j) {
+        int32_t col = conn[(int64_t)j * E + e];
+        int32_t lo = lo0, hi = hi0;
+        while (lo < hi) {
+            int32_t mid = lo + ((hi - lo) >> 1);
+            if (colind[mid] < col) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo >= hi0 || colind[lo] != col) {
+            atomicOr(err, kErrSlotMissing);
+            lo = lo0;
+        }
+        slot[((int64_t)i * npe + j) * E + e] = lo;
+    }
+}
+
+// ---- colouring ----------------------------------------------------------------------
+__device__ __forceinline__ uint32_t prio_hash(uint32_t x)
+{
+    // integer finaliser (xor-shift-multiply), used only to order elements randomly
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+// One Jones-Plassmann round.  An uncoloured element whose (priority, id) beats every
+// uncoloured neighbour takes the smallest colour unused by its coloured neighbours.
+// Reads cin, writes cout (double buffering keeps the result independent of timing).
+__global__ void k_colour_round(const int32_t *__restrict__ cin, int32_t *__restrict__ cout,
+                               const int32_t *__restrict__ conn, int64_t E, int nvert,
+                               const int32_t *__restrict__ n2e_ptr, const int32_t *__restrict__ n2e,
+                               int *remaining, int *err)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t c = cin[e];
+    if (c >= 0) {
+        cout[e] = c;
+        return;
+    }
+    uint32_t pe = prio_hash((uint32_t)e);
+    uint64_t m0 = 0, m1 = 0;
+    for (int k = 0; k < nvert; ++k) {
+        int32_t n = conn[(int64_t)k * E + e];
+        for (int32_t t = n2e_ptr[n]; t < n2e_ptr[n + 1]; ++t) {
+            int32_t e2 = n2e[t];
+            if (e2 == e) continue;
+            int32_t c2 = cin[e2];
+            if (c2 < 0) {
+                uint32_t p2 = prio_hash((uint32_t)e2);
+                if (p2 > pe || (p2 == pe && e2 > e)) {
+                    cout[e] = -1;
+                    atomicAdd(remaining, 1);
+                    return;
+                }
+            } else if (c2 < 64) {
+                m0 |= 1ull << c2;
+            } else {
+                m1 |= 1ull << (c2 - 64);
+            }
+        }
+    }
+    int col;
+    if (~m0) col = __builtin_ctzll(~m0);
+    else if (~m1) col = 64 + __builtin_ctzll(~m1);
+    else {
+        atomicOr(err, kErrColours);
+        col = kMaxColours - 1;
+    }
+    cout[e] = col;
+}
+
+__global__ __launch_bounds__(kThreads) void k_colour_hist(const int32_t *__restrict__ colour,
+                                                          int64_t E, int64_t nblk,
+                                                          int32_t *__restrict__ hist)
+{
+    __shared__ int32_t h[kMaxColours];
+    for (int c = threadIdx.x; c < kMaxColours; c += kThreads) h[c] = 0;
+    __syncthreads();
+    int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e < E) atomicAdd(&h[colour[e]], 1);
+    __syncthreads();
+    for (int c = threadIdx.x; c < kMaxColours; c += kThreads)
+        hist[(int64_t)c * nblk + blockIdx.x] = h[c];
+}
+
+__global__ __launch_bounds__(kThreads) void k_colour_scatter(const int32_t *__restrict__ colour,
+                                                             int64_t E, int64_t nblk,
+                                                             const int64_t *__restrict__ off,
+                                                             int32_t *__restrict__ perm)
+{
+    __shared__ int32_t sc[kThreads];
+    int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    int32_t c = e < E ? colour[e] : -1;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    if (e >= E) return;
+    int rank = 0;
+    for (int t = 0; t < (int)threadIdx.x; ++t) rank += (sc[t] == c);
+    perm[off[(int64_t)c * nblk + blockIdx.x] + rank] = (int32_t)e;
+}
+
+__global__ void k_colour_ptr(const int64_t *__restrict__ off, int64_t nblk, int64_t *__restrict__ out)
+{
+    int c = threadIdx.x;
+    if (c <= kMaxColours) out[c] = off[(int64_t)c * nblk];
+}
+
+__global__ void k_gather_cols(const int32_t *__restrict__ src, const int32_t *__restrict__ perm,
+                              int32_t *__restrict__ dst, int64_t K, int64_t E)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K * E) return;
+    int64_t k = t / E, i = t - k * E;
+    dst[t] = src[k * E + perm[i]];
+}
+
+// RAII for temporaries of the build
+struct Tmp {
+    std::vector<void *> ptrs;
+    hipStream_t s;
+    explicit Tmp(hipStream_t st) : s(st) {}
+    template <class T>
+    int get(T **p, size_t count)
+    {
+        void *q = nullptr;
+        hipError_t e = hipMallocAsync(&q, count ? count * sizeof(T) : 8, s);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? FEM_ERR_OOM : FEM_ERR_HIP,
+                        std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        ptrs.push_back(q);
+        *p = (T *)q;
+        return FEM_OK;
+    }
+    ~Tmp()
+    {
+        for (void *q : ptrs) hipFreeAsync(q, s);
+    }
+};
+
+int read_err(int *d_err, hipStream_t s, int *h_err)
+{
+    FEM_HIP_TRY(hipMemcpyAsync(h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    return FEM_OK;
+}
+
+}  // namespace
+
+int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipStream_t s)
+{
+    (void)flags;
+    const int64_t E = p->n_elems, N = p->n_nodes;
+    const int npe = p->npe;
+    const int64_t EK = E * npe;
+    Tmp tmp(s);
+    int *d_err = nullptr;
+    FEM_TRY(tmp.get(&d_err, 1));
+    FEM_HIP_TRY(hipMemsetAsync(d_err, 0, sizeof(int), s));
+
+    // 1. incidence
+    int32_t *deg = nullptr, *cursor = nullptr;
+    int64_t *off64 = nullptr;
+    FEM_TRY(tmp.get(&deg, N));
+    FEM_TRY(tmp.get(&cursor, N));
+    FEM_TRY(tmp.get(&off64, N + 1));
+    FEM_HIP_TRY(hipMemsetAsync(deg, 0, sizeof(int32_t) * N, s));
+    FEM_HIP_TRY(hipMemsetAsync(cursor, 0, sizeof(int32_t) * N, s));
+    if (EK > 0)
+        hipLaunchKernelGGL(k_count_incidence, dim3(grid_for(EK, kThreads)), dim3(kThreads), 0, s,
+                           m->conn, E, npe, N, deg, d_err);
+    FEM_TRY(scan_counts_i64(deg, off64, N, s));
+    FEM_TRY(pattern_alloc(p, (void **)&p->n2e_ptr, sizeof(int32_t) * (N + 1)));
+    FEM_TRY(pattern_alloc(p, (void **)&p->n2e, sizeof(int32_t) * EK));
+    hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for(N + 1, kThreads)), dim3(kThreads), 0, s, off64,
+                       p->n2e_ptr, N + 1);
+    int h_err = 0;
+    FEM_TRY(read_err(d_err, s, &h_err));
+    if (h_err & kErrConnRange)
+        return fail(FEM_ERR_INVALID_ARG, "connectivity entry outside [0, n_nodes)");
+    if (EK > 0)
+        hipLaunchKernelGGL(k_fill_n2e, dim3(grid_for(EK, kThreads)), dim3(kThreads), 0, s, m->conn,
+                           E, npe, p->n2e_ptr, cursor, p->n2e);
+
+    // 2. rows
+    int32_t *rowlen = nullptr;
+    FEM_TRY(tmp.get(&rowlen, N));
+    hipLaunchKernelGGL(k_row_count, dim3((unsigned)N), dim3(kRowThreads), 0, s, p->n2e_ptr, p->n2e,
+                       m->conn, E, npe, rowlen, d_err);
+    FEM_TRY(scan_counts_i64(rowlen, off64, N, s));
+    int64_t nnz_nodes = 0;
+    FEM_HIP_TRY(hipMemcpyAsync(&nnz_nodes, off64 + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FEM_TRY(read_err(d_err, s, &h_err));
+    if (h_err & kErrRowCap)
+        return fail(FEM_ERR_UNSUPPORTED, "a pattern row has more than 2048 candidate entries");
+    const int64_t nc = p->ncomp;
+    if (nnz_nodes > INT32_MAX || nnz_nodes * nc * nc > INT32_MAX)
+        return fail(FEM_ERR_INDEX_OVERFLOW, "nnz does not fit int32 (" +
+                                                std::to_string(nnz_nodes * nc * nc) + ")");
+    p->nnz_nodes = nnz_nodes;
+    p->nnz = nnz_nodes * nc * nc;
+    FEM_TRY(pattern_alloc(p, (void **)&p->rowptr_n, sizeof(int32_t) * (N + 1)));
+    FEM_TRY(pattern_alloc(p, (void **)&p->colind_n, sizeof(int32_t) * nnz_nodes));
+    hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for(N + 1, kThreads)), dim3(kThreads), 0, s, off64,
+                       p->rowptr_n, N + 1);
+    hipLaunchKernelGGL(k_row_fill, dim3((unsigned)N), dim3(kRowThreads), 0, s, p->n2e_ptr, p->n2e,
+                       m->conn, E, npe, p->rowptr_n, p->colind_n);
+
+    // 3. slot map
+    FEM_TRY(pattern_alloc(p, (void **)&p->slot, sizeof(int32_t) * EK * npe));
+    if (EK > 0)
+        hipLaunchKernelGGL(k_slot_map, dim3(grid_for(EK, kThreads)), dim3(kThreads), 0, s, m->conn,
+                           E, npe, p->rowptr_n, p->colind_n, p->slot, d_err);
+
+    // 4. colouring
+    const int nvert = p->dim + 1;
+    int32_t *cA = nullptr, *cB = nullptr;
+    FEM_TRY(pattern_alloc(p, (void **)&p->colour, sizeof(int32_t) * E));
+    FEM_TRY(tmp.get(&cA, E));
+    cB = p->colour;
+    if (E > 0)
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(E, kThreads)), dim3(kThreads), 0, s, cA, E,
+                           (int32_t)-1);
+    constexpr int kRoundsPerCheck = 4;
+    int *d_rem = nullptr;
+    FEM_TRY(tmp.get(&d_rem, kRoundsPerCheck));
+    int rounds = 0;
+    int32_t *cur = cA, *nxt = cB;
+    while (E > 0) {
+        FEM_HIP_TRY(hipMemsetAsync(d_rem, 0, sizeof(int) * kRoundsPerCheck, s));
+        for (int r = 0; r < kRoundsPerCheck; ++r) {
+            hipLaunchKernelGGL(k_colour_round, dim3(grid_for(E, kThreads)), dim3(kThreads), 0, s,
+                               cur, nxt, m->conn, E, nvert, p->n2e_ptr, p->n2e, d_rem + r, d_err);
+            std::swap(cur, nxt);
+            ++rounds;
+        }
+        int h_rem[kRoundsPerCheck];
+        FEM_HIP_TRY(hipMemcpyAsync(h_rem, d_rem, sizeof(h_rem), hipMemcpyDeviceToHost, s));
+        FEM_TRY(read_err(d_err, s, &h_err));
+        if (h_err & kErrColours)
+            return fail(FEM_ERR_UNSUPPORTED, "element colouring needs more than 128 colours");
+        if (h_rem[kRoundsPerCheck - 1] == 0) break;
+        if (rounds > 100000) return fail(FEM_ERR_HIP, "colouring did not terminate");
+    }
+    if (E > 0 && cur != p->colour)
+        FEM_HIP_TRY(hipMemcpyAsync(p->colour, cur, sizeof(int32_t) * E, hipMemcpyDeviceToDevice, s));
+
+    // 5. stable sort by colour
+    const int64_t nblk = (E + kThreads - 1) / kThreads;
+    int32_t *hist = nullptr;
+    int64_t *hoff = nullptr, *cptr = nullptr;
+    FEM_TRY(tmp.get(&hist, (size_t)kMaxColours * nblk));
+    FEM_TRY(tmp.get(&hoff, (size_t)kMaxColours * nblk + 1));
+    FEM_TRY(tmp.get(&cptr, kMaxColours + 1));
+    FEM_TRY(pattern_alloc(p, (void **)&p->perm, sizeof(int32_t) * E));
+    std::vector<int64_t> h_cptr(kMaxColours + 1, 0);
+    if (E > 0) {
+        hipLaunchKernelGGL(k_colour_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, p->colour, E,
+                           nblk, hist);
+        FEM_TRY(scan_counts_i64(hist, hoff, (int64_t)kMaxColours * nblk, s));
+        hipLaunchKernelGGL(k_colour_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, p->colour,
+                           E, nblk, hoff, p->perm);
+        hipLaunchKernelGGL(k_colour_ptr, dim3(1), dim3(kMaxColours + 1), 0, s, hoff, nblk, cptr);
+        FEM_HIP_TRY(hipMemcpyAsync(h_cptr.data(), cptr, sizeof(int64_t) * (kMaxColours + 1),
+                                   hipMemcpyDeviceToHost, s));
+    }
+    // 6. colour-ordered copies
+    FEM_TRY(pattern_alloc(p, (void **)&p->conn_perm, sizeof(int32_t) * EK));
+    FEM_TRY(pattern_alloc(p, (void **)&p->slot_perm, sizeof(int32_t) * EK * npe));
+    if (E > 0) {
+        hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(EK, kThreads)), dim3(kThreads), 0, s,
+                           m->conn, p->perm, p->conn_perm, (int64_t)npe, E);
+        hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(EK * npe, kThreads)), dim3(kThreads), 0, s,
+                           p->slot, p->perm, p->slot_perm, (int64_t)npe * npe, E);
+    }
+    FEM_HIP_TRY(hipGetLastError());
+    FEM_TRY(read_err(d_err, s, &h_err));
+    if (h_err & kErrSlotMissing) return fail(FEM_ERR_HIP, "internal: slot map lookup failed");
+
+    int ncol = 0;
+    for (int c = 0; c < kMaxColours; ++c)
+        if (h_cptr[c + 1] > h_cptr[c]) ncol = c + 1;
+    p->n_colours = ncol;
+    p->colour_ptr.assign(h_cptr.begin(), h_cptr.begin() + ncol + 1);
+    (void)rounds;
+
+    // longest dof row (host scan over a small copy is avoided: derive from the node rows)
+    int32_t *h_rp = nullptr;
+    std::vector<int32_t> rp(N + 1);
+    FEM_HIP_TRY(hipMemcpyAsync(rp.data(), p->rowptr_n, sizeof(int32_t) * (N + 1),
+                               hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    (void)h_rp;
+    int32_t mr = 0;
+    for (int64_t i = 0; i < N; ++i) mr = std::max(mr, rp[i + 1] - rp[i]);
+    p->max_row = mr * (int32_t)nc;
+    return FEM_OK;
+}
+
+}  // namespace fem

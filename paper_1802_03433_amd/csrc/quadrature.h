@@ -1,0 +1,79 @@
+// Quadrature rules and reference-element tables of the device kernels.
+//
+// The paper evaluates the integrand at integration points, one thread per point
+// (Sec. 5, Fig. 2); it names no rule.  The rules used here are the symmetric
+// positive-weight rules of the degree each form needs, in barycentric coordinates with
+// weights normalised to sum to 1 (the element volume multiplies them):
+//   triangle, degree 2, 3 points:    (2/3, 1/6, 1/6) and permutations, w = 1/3
+//   tetrahedron, degree 2, 4 points: (a, b, b, b) and permutations, w = 1/4,
+//                                    a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20
+//   tetrahedron, degree 5, 14 points (the positive rule with orbits
+//     S31(a1), S31(a2), S22(b); Walkington 2000, Keast 1986 family):
+//     a1 = 0.0927352503108912, w1 = 0.0734930431163619 (x4)
+//     a2 = 0.3108859192633006, w2 = 0.1126879257180159 (x4)
+//     b  = 0.0455037041256496, w3 = 0.0425460207770815 (x6)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fem {
+namespace quad {
+
+// ---- P1 rules: lam(q, k) = k-th barycentric coordinate of point q ------------------
+template <int D>
+struct P1Rule;
+
+template <>
+struct P1Rule<2> {
+    static constexpr int nq = 3;
+    __host__ __device__ static constexpr double lam(int q, int k)
+    {
+        return q == k ? 0.66666666666666667 : 0.16666666666666667;
+    }
+    __host__ __device__ static constexpr double w(int) { return 0.33333333333333333; }
+};
+
+template <>
+struct P1Rule<3> {
+    static constexpr int nq = 4;
+    __host__ __device__ static constexpr double lam(int q, int k)
+    {
+        return q == k ? 0.58541019662496845 : 0.13819660112501052;
+    }
+    __host__ __device__ static constexpr double w(int) { return 0.25; }
+};
+
+// Reference P1 mass table  M_ij = sum_q w_q lam_i(q) lam_j(q)  (quadrature of the mass
+// term of Eq. (2); exact for this degree-2 integrand).
+template <int D>
+__host__ __device__ constexpr double p1_mass(int i, int j)
+{
+    double s = 0.0;
+    for (int q = 0; q < P1Rule<D>::nq; ++q) s += P1Rule<D>::w(q) * P1Rule<D>::lam(q, i) * P1Rule<D>::lam(q, j);
+    return s;
+}
+
+// ---- 14-point degree-5 tetrahedron rule ---------------------------------------------
+struct Tet14 {
+    static constexpr int nq = 14;
+    static constexpr double a1 = 0.0927352503108912, w1 = 0.0734930431163619;
+    static constexpr double a2 = 0.3108859192633006, w2 = 0.1126879257180159;
+    static constexpr double b = 0.0455037041256496, w3 = 0.0425460207770815;
+    __host__ __device__ static constexpr double lam(int q, int k)
+    {
+        if (q < 4) return k == q ? 1.0 - 3.0 * a1 : a1;
+        if (q < 8) return k == q - 4 ? 1.0 - 3.0 * a2 : a2;
+        // 6-point orbit: pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) carry b
+        constexpr int pi[6] = {0, 0, 0, 1, 1, 2};
+        constexpr int pj[6] = {1, 2, 3, 2, 3, 3};
+        int p = q - 8;
+        return (k == pi[p] || k == pj[p]) ? b : 0.5 - b;
+    }
+    __host__ __device__ static constexpr double w(int q)
+    {
+        return q < 4 ? w1 : (q < 8 ? w2 : w3);
+    }
+};
+
+}  // namespace quad
+}  // namespace fem

@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI (no GPU needed): every function declared in
+include/fem.h is exported by libfemhip.so, and argument errors are reported before any
+device work."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "fem.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(fem_[a-z_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1802_03433_amd import _lib
+
+    return _lib
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for n in ("fem_build_pattern", "fem_assemble", "fem_assemble_backward"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared_functions()
+    assert names, "no declarations parsed"
+    for n in names:
+        assert hasattr(L.lib, n), f"{n} not exported"
+    assert sorted(L.EXPORTS) == names
+
+
+def test_error_strings(L):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.lib.fem_error_string(code)
+    assert L.lib.fem_error_string(123) == b"unknown error code"
+
+
+def test_null_arguments_rejected_before_device_work(L):
+    out = ctypes.c_void_p()
+    assert L.lib.fem_build_pattern(None, 1, 0, ctypes.byref(out), None) == -1
+    assert b"NULL" in L.lib.fem_last_error_message()
+    m = L.fem_mesh()
+    m.dim, m.order, m.n_nodes, m.n_elems = 4, 1, 10, 1
+    assert L.lib.fem_build_pattern(ctypes.byref(m), 1, 0, ctypes.byref(out), None) == -1
+    m.dim, m.order = 2, 2
+    assert L.lib.fem_build_pattern(ctypes.byref(m), 1, 0, ctypes.byref(out), None) == -2
+    m.dim, m.order = 3, 1
+    m.conn = None
+    assert L.lib.fem_build_pattern(ctypes.byref(m), 1, 0, ctypes.byref(out), None) == -1
+    m.conn = 8  # non-null, never dereferenced: ncomp is rejected first
+    assert L.lib.fem_build_pattern(ctypes.byref(m), 2, 0, ctypes.byref(out), None) == -1
+    m.dim = 2
+    assert L.lib.fem_build_pattern(ctypes.byref(m), 3, 0, ctypes.byref(out), None) == -2
+    # sizes that overflow int32 indexing are refused from the descriptor alone
+    m.dim, m.n_nodes, m.n_elems = 3, 10, 2 ** 28
+    assert L.lib.fem_build_pattern(ctypes.byref(m), 1, 0, ctypes.byref(out), None) == -4
+    assert not out
+    f = L.fem_form()
+    assert L.lib.fem_assemble(None, ctypes.byref(m), ctypes.byref(f), None, None, None, 0, None) == -1
+    assert L.lib.fem_pattern_query(None, None) == -1
+    L.lib.fem_pattern_destroy(None)  # no-op
