@@ -69,6 +69,13 @@ extern "C" {
                                      bitwise reproducible run to run */
 #define FEM_ACCUMULATE 0x2u       /* add into the outputs instead of overwriting them */
 #define FEM_VALIDATE 0x4u         /* device-side input checks (synchronises) */
+#define FEM_ELEMENT_SCATTER 0x10u /* scatter each element straight to HBM, without the
+                                     workgroup (tile) combining stage; a reference path
+                                     for comparisons (atomic only unless the pattern has
+                                     an element colouring) */
+/* fem_build_pattern: elements per tile of the combined scatter, as log2 in bits 8..11
+   (0 = default 256; accepted 64..1024) */
+#define FEM_TILE_LOG2(k) (((unsigned)(k) & 0xfu) << 8)
 
 typedef struct fem_pattern fem_pattern; /* opaque, library-owned */
 

@@ -29,6 +29,11 @@ SCATTER_ATOMIC = 0x0
 SCATTER_COLOURED = 0x1
 ACCUMULATE = 0x2
 VALIDATE = 0x4
+ELEMENT_SCATTER = 0x10
+
+
+def TILE_LOG2(k: int) -> int:
+    return (int(k) & 0xF) << 8
 
 # Every extern "C" function of include/fem.h (checked by the tests).
 EXPORTS = (

@@ -36,7 +36,7 @@ def _need(t: torch.Tensor, dtype, name: str):
         raise ValueError(f"{name} must be contiguous")
 
 
-def _flags(scatter: str, accumulate: bool, validate: bool) -> int:
+def _flags(scatter: str, accumulate: bool, validate: bool, element_scatter: bool = False) -> int:
     if scatter not in _SCATTER:
         raise ValueError(f"scatter must be one of {list(_SCATTER)}")
     f = _SCATTER[scatter]
@@ -44,6 +44,8 @@ def _flags(scatter: str, accumulate: bool, validate: bool) -> int:
         f |= L.ACCUMULATE
     if validate:
         f |= L.VALIDATE
+    if element_scatter:
+        f |= L.ELEMENT_SCATTER
     return f
 
 
@@ -101,11 +103,17 @@ class Form:
 class Pattern:
     """Owning wrapper of a fem_pattern handle (sparsity, slot map, colouring)."""
 
-    def __init__(self, mesh: Mesh, ncomp: int = 1, validate: bool = False):
+    def __init__(self, mesh: Mesh, ncomp: int = 1, validate: bool = False, tile: int | None = None):
+        """tile: elements per tile of the combined scatter (power of two, 64..1024)."""
         self.mesh = mesh
         self._h = ctypes.c_void_p()
         ms = mesh.cstruct()
         flags = L.VALIDATE if validate else 0
+        if tile is not None:
+            k = int(tile).bit_length() - 1
+            if tile <= 0 or (1 << k) != tile:
+                raise ValueError("tile must be a power of two")
+            flags |= L.TILE_LOG2(k)
         rc = L.lib.fem_build_pattern(ctypes.byref(ms), int(ncomp), flags, ctypes.byref(self._h),
                                      _stream_ptr(mesh.coords.device))
         L.check(rc, "fem_build_pattern")
@@ -155,8 +163,10 @@ class Pattern:
 
 def assemble(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tensor,
              values: torch.Tensor | None = None, rhs: torch.Tensor | None = None,
-             scatter: str = "atomic", accumulate: bool = False, validate: bool = False):
-    """fem_assemble; returns (values [nnz], rhs [n_rows] or None)."""
+             scatter: str = "atomic", accumulate: bool = False, validate: bool = False,
+             element_scatter: bool = False):
+    """fem_assemble; returns (values [nnz], rhs [n_rows] or None).
+    element_scatter: bypass the tile combining stage (reference path)."""
     _need(coef, torch.float64, "coef")
     dev = mesh.coords.device
     if values is None:
@@ -168,7 +178,8 @@ def assemble(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tensor,
         _need(rhs, torch.float64, "rhs")
     ms, fs = mesh.cstruct(), form.cstruct()
     rc = L.lib.fem_assemble(pattern.handle, ctypes.byref(ms), ctypes.byref(fs), _ptr(coef),
-                            _ptr(values), _ptr(rhs), _flags(scatter, accumulate, validate),
+                            _ptr(values), _ptr(rhs),
+                            _flags(scatter, accumulate, validate, element_scatter),
                             _stream_ptr(dev))
     L.check(rc, "fem_assemble")
     return values, rhs
@@ -179,7 +190,8 @@ def assemble_backward(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tens
                       want_coef: bool = True, want_coords: bool = True,
                       scatter: str = "atomic", accumulate: bool = False,
                       grad_coef: torch.Tensor | None = None,
-                      grad_coords: torch.Tensor | None = None):
+                      grad_coords: torch.Tensor | None = None,
+                      element_scatter: bool = False):
     """fem_assemble_backward; returns (grad_coef [ncoef][E] or None, grad_coords or None)."""
     _need(coef, torch.float64, "coef")
     dev = mesh.coords.device
@@ -195,7 +207,8 @@ def assemble_backward(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tens
                                      _ptr(coef), _ptr(grad_values), _ptr(grad_rhs),
                                      _ptr(grad_coef if want_coef else None),
                                      _ptr(grad_coords if want_coords else None),
-                                     _flags(scatter, accumulate, False), _stream_ptr(dev))
+                                     _flags(scatter, accumulate, False, element_scatter),
+                                     _stream_ptr(dev))
     L.check(rc, "fem_assemble_backward")
     return (grad_coef if want_coef else None), (grad_coords if want_coords else None)
 

@@ -125,7 +125,7 @@ int fem_pattern_query(const fem_pattern *p, fem_pattern_info *info)
     info->nnz_nodes = p->nnz_nodes;
     info->ncomp = p->ncomp;
     info->npe = p->npe;
-    info->n_colours = p->n_colours;
+    info->n_colours = p->has_tiles ? p->n_tile_colours : p->n_colours;
     info->max_row = p->max_row;
     info->device_bytes = p->device_bytes;
     return FEM_OK;
@@ -181,13 +181,30 @@ int fem_pattern_export(const fem_pattern *p, int32_t *rowptr, int32_t *colind, v
     return FEM_OK;
 }
 
+namespace {
+// element colour in scatter order: tile colour, then colour inside the tile
+__global__ void k_tile_elem_colour(const int32_t *__restrict__ tcol, const uint8_t *__restrict__ esub,
+                                   int64_t E, int T, int32_t *__restrict__ out)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < E) out[e] = tcol[e / T] * kMaxSubColours + esub[e];
+}
+}  // namespace
+
 int fem_pattern_colours(const fem_pattern *p, int32_t *colour, void *stream)
 {
     clear_error();
     if (!p || (!colour && p->n_elems > 0)) return fail(FEM_ERR_INVALID_ARG, "NULL argument");
-    if (p->n_elems > 0)
+    if (p->n_elems == 0) return FEM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->has_tiles) {
+        hipLaunchKernelGGL(k_tile_elem_colour, dim3(grid_for(p->n_elems, 256)), dim3(256), 0, s,
+                           p->tile_colour, p->esub, p->n_elems, p->tile, colour);
+        FEM_HIP_TRY(hipGetLastError());
+    } else {
         FEM_HIP_TRY(hipMemcpyAsync(colour, p->colour, sizeof(int32_t) * p->n_elems,
-                                   hipMemcpyDeviceToDevice, (hipStream_t)stream));
+                                   hipMemcpyDeviceToDevice, s));
+    }
     return FEM_OK;
 }
 
@@ -210,19 +227,29 @@ int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *for
     FEM_TRY(check_mesh(mesh, true));
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));
-    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE))
+    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER))
         return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
     if (!values && p->nnz > 0) return fail(FEM_ERR_INVALID_ARG, "values is NULL");
     if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
     if (form->load != FEM_LOAD_NONE && !rhs && p->n_rows > 0)
         return fail(FEM_ERR_INVALID_ARG, "rhs is NULL but the form has a load");
     hipStream_t s = (hipStream_t)stream;
-    if (!(flags & FEM_ACCUMULATE)) {
-        FEM_TRY(fill_zero_f64(values, p->nnz, s));
-        if (rhs) FEM_TRY(fill_zero_f64(rhs, p->n_rows, s));
+    const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
+    const bool accumulate = (flags & FEM_ACCUMULATE) != 0;
+    double *rhs_ok = (form->load == FEM_LOAD_NONE) ? nullptr : rhs;
+    if (flags & FEM_VALIDATE) FEM_TRY(validate_elements(mesh, s));
+    const bool tiles = p->has_tiles && !(flags & FEM_ELEMENT_SCATTER);
+    if (!tiles && coloured && !p->has_element_colouring)
+        return fail(FEM_ERR_UNSUPPORTED, "per-element coloured scatter needs an element colouring");
+    if (!accumulate) {
+        // the coloured tile scatter stores (rather than adds) on its first write of every
+        // slot, so only the RHS of nodes in no element needs clearing
+        if (!(tiles && coloured)) FEM_TRY(fill_zero_f64(values, p->nnz, s));
+        if (rhs_ok && (!(tiles && coloured) || p->has_isolated_nodes))
+            FEM_TRY(fill_zero_f64(rhs_ok, p->n_rows, s));
     }
-    const double *rhs_ok = (form->load == FEM_LOAD_NONE) ? nullptr : rhs;
-    return p1_forward(p, mesh, form, coef, values, const_cast<double *>(rhs_ok), flags, s);
+    if (tiles) return p1_tile_forward(p, mesh, form, coef, values, rhs_ok, flags, s);
+    return p1_forward(p, mesh, form, coef, values, rhs_ok, flags & ~FEM_VALIDATE, s);
 }
 
 int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_form *form,
@@ -233,14 +260,23 @@ int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_
     FEM_TRY(check_mesh(mesh, true));
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));
-    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE))
+    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER))
         return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
     if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
     hipStream_t s = (hipStream_t)stream;
-    if (!(flags & FEM_ACCUMULATE) && grad_coords)
+    const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
+    const bool accumulate = (flags & FEM_ACCUMULATE) != 0;
+    if (flags & FEM_VALIDATE) FEM_TRY(validate_elements(mesh, s));
+    const bool tiles = p->has_tiles && !(flags & FEM_ELEMENT_SCATTER);
+    if (!tiles && coloured && !p->has_element_colouring)
+        return fail(FEM_ERR_UNSUPPORTED, "per-element coloured scatter needs an element colouring");
+    if (!accumulate && grad_coords && (!(tiles && coloured) || p->has_isolated_nodes))
         FEM_TRY(fill_zero_f64(grad_coords, p->dim * p->n_nodes, s));
     if (!grad_coef && !grad_coords) return FEM_OK;
     const double *grhs = (form->load == FEM_LOAD_NONE) ? nullptr : grad_rhs;
+    if (tiles)
+        return p1_tile_backward(p, mesh, form, coef, grad_values, grhs, grad_coef, grad_coords,
+                                flags, s);
     return p1_backward(p, mesh, form, coef, grad_values, grhs, grad_coef, grad_coords, flags, s);
 }
 

@@ -52,6 +52,10 @@ struct DevBuf {
 
 // Colour limit of the first-fit colouring (two 64-bit masks per element).
 constexpr int kMaxColours = 128;
+// Longest node row the tile plan handles (row positions kept in one 64-bit mask).
+constexpr int kTileMaxRow = 64;
+// Intra-tile colours (8-bit element field, 64-bit masks).
+constexpr int kMaxSubColours = 64;
 // Largest candidate list (sum of npe over a node's elements) a pattern row may have.
 constexpr int kRowCap = 2048;
 
@@ -79,6 +83,29 @@ struct fem_pattern {
     int32_t *perm = nullptr;          // [E] elements sorted by colour, ascending within one
     int32_t *conn_perm = nullptr;     // [npe][E] conn in perm order
     int32_t *slot_perm = nullptr;     // [npe*npe][E] slot map in perm order
+    bool has_element_colouring = false;
+    bool has_isolated_nodes = false;  // nodes in no element (rows left empty)
+
+    // ---- tile plan: consecutive ranges of `tile` elements combined in LDS ----
+    bool has_tiles = false;
+    int32_t tile = 0;              // elements per tile (= threads per workgroup)
+    int64_t n_tiles = 0;
+    int32_t tile_max_nodes = 0;    // largest distinct-node count of a tile
+    int32_t tile_max_slots = 0;    // largest distinct-slot count of a tile
+    int32_t *tnode_ptr = nullptr;  // [n_tiles+1] offsets into tnode
+    int32_t *tnode = nullptr;      // distinct nodes of each tile, ascending
+    uint64_t *trun = nullptr;      // per tile node: bit p set <=> the tile writes row position p
+    uint64_t *tfirst = nullptr;    // per tile node: bits of trun this tile writes first
+                                   // (lowest tile colour among the tiles writing the slot)
+    uint8_t *trfirst = nullptr;    // per tile node: 1 if this tile writes the node's RHS first
+    uint16_t *enode = nullptr;     // [npe][E] index of conn(e,k) in its tile's node list
+    uint8_t *epos = nullptr;       // [npe*npe][E] position of conn(e,j) in the row of conn(e,i)
+    uint8_t *esub = nullptr;       // [E] colour of the element inside its tile
+    int32_t *tile_nsub = nullptr;  // [n_tiles] number of intra-tile colours
+    int32_t *tile_colour = nullptr;  // [n_tiles]
+    int32_t *tile_perm = nullptr;    // [n_tiles] tiles sorted by colour
+    int32_t n_tile_colours = 0;
+    std::vector<int64_t> tile_colour_ptr;  // host [n_tile_colours+1]
     std::vector<fem::DevBuf> owned;
     int64_t device_bytes = 0;
 };
@@ -96,6 +123,23 @@ int fill_zero_f64(double *p, int64_t n, hipStream_t s);
 
 // pattern construction (pattern.hip)
 int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipStream_t s);
+int build_element_colouring(fem_pattern *p, const int32_t *conn, hipStream_t s);
+// tile plan (tiles.hip); returns FEM_ERR_UNSUPPORTED when the mesh does not fit its limits
+int build_tile_plan(fem_pattern *p, const int32_t *conn, int tile, hipStream_t s);
+// integer colour sort helpers shared by element and tile colouring (pattern.hip)
+int sort_by_colour(const int32_t *colour, int64_t n, int32_t *perm, std::vector<int64_t> &ptr,
+                   hipStream_t s);
+int jp_rounds_check(int *d_rem, int nrounds, int *d_err, hipStream_t s, bool *done);
+
+// tile-combined P1 launchers (p1_tile.hip)
+int p1_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,
+                    double *values, double *rhs, unsigned flags, hipStream_t s);
+int p1_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
+                     const double *coef, const double *gvalues, const double *grhs,
+                     double *gcoef, double *gcoords, unsigned flags, hipStream_t s);
+
+// device check of the element Jacobians (p1.hip; reads the vertex coordinates only)
+int validate_elements(const fem_mesh *m, hipStream_t s);
 
 // assembly launchers (p1.hip)
 int p1_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,

@@ -409,7 +409,47 @@ void dispatch_bwd(const fem_pattern *p, const P1BwdArgs &b, int load, bool colou
     }
 }
 
+__global__ void k_p1_validate(const double *__restrict__ coords, int64_t N,
+                              const int32_t *__restrict__ conn, int64_t E, int D, int *err)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double x[4][3] = {};
+    for (int k = 0; k <= D; ++k)
+        for (int d = 0; d < D; ++d) x[k][d] = coords[d * N + conn[k * E + e]];
+    double det;
+    if (D == 2) {
+        det = (x[1][0] - x[0][0]) * (x[2][1] - x[0][1]) - (x[2][0] - x[0][0]) * (x[1][1] - x[0][1]);
+    } else {
+        double a[3][3];
+        for (int d = 0; d < 3; ++d)
+            for (int m = 0; m < 3; ++m) a[d][m] = x[m + 1][d] - x[0][d];
+        det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+              a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+              a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+    }
+    if (!(det != 0.0) || !isfinite(det)) atomicOr(err, 1);
+}
+
 }  // namespace
+
+// Device-side check that no element has a zero (or non-finite) Jacobian determinant.
+// Reads the vertex coordinates only; synchronises the stream.
+int validate_elements(const fem_mesh *m, hipStream_t s)
+{
+    if (m->n_elems == 0) return FEM_OK;
+    int *d_err = nullptr;
+    FEM_HIP_TRY(hipMallocAsync((void **)&d_err, sizeof(int), s));
+    FEM_HIP_TRY(hipMemsetAsync(d_err, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_p1_validate, dim3(grid_for(m->n_elems, kThreads)), dim3(kThreads), 0, s,
+                       m->coords, m->n_nodes, m->conn, m->n_elems, (int)m->dim, d_err);
+    int h = 0;
+    FEM_HIP_TRY(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    (void)hipFreeAsync(d_err, s);
+    if (h) return fail(FEM_ERR_DEGENERATE, "element with zero Jacobian determinant");
+    return FEM_OK;
+}
 
 int p1_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,
                double *values, double *rhs, unsigned flags, hipStream_t s)

@@ -1,0 +1,629 @@
+// Tile-combined P1 assembly and adjoint (the default path for P1 meshes whose rows hold
+// at most 64 entries).
+//
+// One workgroup per tile of `tile` consecutive elements, one element per thread.  Phases:
+//   A  stage the tile's distinct nodes in LDS: coordinates, row offsets, row-position
+//      masks; expand the masks into the tile's ascending list of distinct CSR slots
+//      (LDS), zero the LDS accumulators,
+//   B  per element (registers): geometry, gradients, quadrature of the form and the load
+//      (same formulas as the per-element kernels), then add the element matrix and vector
+//      into the LDS accumulators (Alg. 1's shared-memory atomicAdd step): LDS FP64 atomics
+//      for the atomic variant; intra-tile colour phases, no atomics, for the coloured one,
+//   C  one global update per distinct slot and node, coalesced (the slot list is sorted):
+//      device-scope FP64 atomics, or -- colour by colour -- plain stores (first writer of
+//      a slot) and read-modify-writes.
+#include "fem_internal.h"
+#include "quadrature.h"
+
+namespace fem {
+
+namespace {
+
+enum Mode : int { kAtomic = 0, kColoured = 1 };
+
+struct TileArgs {
+    const double *coords;
+    int64_t N, E;
+    int T;
+    const int32_t *rowptr;
+    const int32_t *tnode_ptr;
+    const int32_t *tnode;
+    const uint64_t *trun;
+    const uint64_t *tfirst;
+    const uint8_t *trfirst;
+    const uint16_t *enode;
+    const uint8_t *epos;
+    const uint8_t *esub;
+    const int32_t *tile_nsub;
+    const int32_t *tile_list;  // coloured: tiles of the launched colour
+    const double *kappa;
+    double c, fconst;
+    int nmax, smax;
+    bool use_first;
+    // forward
+    double *values, *rhs;
+    // adjoint
+    const double *gvalues, *grhs;
+    double *gkappa, *gcoords;
+    bool accumulate;
+};
+
+// LDS carve-up shared by the forward and adjoint kernels
+template <int D>
+struct Lds {
+    double *xs;    // [D][nmax]  coordinates of the tile's nodes
+    double *nacc;  // [D][nmax]  per-node accumulator (rhs uses row 0; adjoint: xbar)
+    double *sacc;  // [smax]     per-slot accumulator (forward) / gathered grad (adjoint)
+    double *gr;    // [nmax]     adjoint: grad_rhs of the tile's nodes
+    uint64_t *rb;  // [nmax]     row-position masks
+    int32_t *ust;  // [nmax]     first slot of each node's run
+    int32_t *us;   // [smax]     slot list (~slot marks a first writer)
+    int32_t *nd;   // [nmax]     node ids
+    int32_t *scan; // [blockDim]
+    uint8_t *nf;   // [nmax]     node first-writer flags
+    __device__ Lds(unsigned char *base, int nmax, int smax)
+    {
+        xs = (double *)base;
+        nacc = xs + D * nmax;
+        sacc = nacc + D * nmax;
+        gr = sacc + smax;
+        rb = (uint64_t *)(gr + nmax);
+        ust = (int32_t *)(rb + nmax);
+        us = ust + nmax;
+        nd = us + smax;
+        scan = nd + nmax;
+        nf = (uint8_t *)(scan + 1024);
+    }
+};
+
+template <int D>
+size_t lds_bytes(int nmax, int smax)
+{
+    return sizeof(double) * (size_t)(2 * D * nmax + smax + nmax) + sizeof(uint64_t) * nmax +
+           sizeof(int32_t) * (size_t)(nmax + smax + nmax + 1024) + (size_t)nmax + 16;
+}
+
+__device__ int wg_scan_excl(int v, int *sh, int *total)
+{
+    const int t = threadIdx.x, n = blockDim.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < n; off <<= 1) {
+        int add = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int incl = sh[t];
+    *total = sh[n - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// Phase A.  Returns the number of distinct slots of the tile.
+template <int D>
+__device__ int stage_tile(const TileArgs &a, Lds<D> &L, int64_t tile, int nn, bool slot_first,
+                          bool gather_grad)
+{
+    const int n0 = a.tnode_ptr[tile];
+    const int bd = blockDim.x;
+    const int per = (nn + bd - 1) / bd;
+    const int k0 = min(nn, (int)threadIdx.x * per), k1 = min(nn, k0 + per);
+    int local = 0;
+    for (int k = k0; k < k1; ++k) {
+        int32_t n = a.tnode[n0 + k];
+        uint64_t r = a.trun[n0 + k];
+        L.nd[k] = n;
+        L.rb[k] = r;
+        L.nf[k] = a.use_first ? a.trfirst[n0 + k] : 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            L.xs[d * a.nmax + k] = a.coords[d * a.N + n];
+            L.nacc[d * a.nmax + k] = 0.0;
+        }
+        if (gather_grad) L.gr[k] = a.grhs ? a.grhs[n] : 0.0;
+        local += __popcll(r);
+    }
+    int total = 0;
+    int off = wg_scan_excl(local, L.scan, &total);
+    {
+        // slot_first: mark the slots this tile writes first (forward, coloured); the
+        // adjoint gathers through the list and must see plain slot numbers
+        for (int k = k0; k < k1; ++k) {
+            L.ust[k] = off;
+            uint64_t r = L.rb[k];
+            uint64_t f = slot_first ? a.tfirst[n0 + k] : 0ull;
+            int32_t base = a.rowptr[L.nd[k]];
+            while (r) {
+                int b = __builtin_ctzll(r);
+                int32_t slot = base + b;
+                L.us[off] = ((f >> b) & 1ull) ? ~slot : slot;
+                L.sacc[off] = 0.0;
+                ++off;
+                r &= r - 1;
+            }
+        }
+    }
+    __syncthreads();
+    if (gather_grad) {
+        // gathered upstream gradient of every distinct slot, coalesced
+        for (int u = threadIdx.x; u < total; u += bd)
+            L.sacc[u] = a.gvalues ? a.gvalues[L.us[u]] : 0.0;
+        __syncthreads();
+    }
+    return total;
+}
+
+template <int D>
+struct Elem {
+    double x[D + 1][D];
+    double inv[D][D];
+    double B[D + 1][D];
+    double det, vol;
+};
+
+template <int D>
+__device__ __forceinline__ void elem_geometry(Elem<D> &g)
+{
+    double J[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int m = 0; m < D; ++m) J[a][m] = g.x[m + 1][a] - g.x[0][a];
+    if constexpr (D == 2) {
+        g.det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        double r = 1.0 / g.det;
+        g.inv[0][0] = J[1][1] * r;
+        g.inv[0][1] = -J[0][1] * r;
+        g.inv[1][0] = -J[1][0] * r;
+        g.inv[1][1] = J[0][0] * r;
+        g.vol = 0.5 * fabs(g.det);
+    } else {
+        double C00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        double C01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        double C02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        double C10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        double C11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        double C12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        double C20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        double C21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        double C22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        g.det = J[0][0] * C00 + J[0][1] * C01 + J[0][2] * C02;
+        double r = 1.0 / g.det;
+        g.inv[0][0] = C00 * r;
+        g.inv[1][0] = C01 * r;
+        g.inv[2][0] = C02 * r;
+        g.inv[0][1] = C10 * r;
+        g.inv[1][1] = C11 * r;
+        g.inv[2][1] = C12 * r;
+        g.inv[0][2] = C20 * r;
+        g.inv[1][2] = C21 * r;
+        g.inv[2][2] = C22 * r;
+        g.vol = fabs(g.det) * (1.0 / 6.0);
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            g.B[m + 1][a] = g.inv[m][a];
+            s += g.inv[m][a];
+        }
+        g.B[0][a] = -s;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void qpoint(const Elem<D> &g, int q, double *xq)
+{
+    using R = quad::P1Rule<D>;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k <= D; ++k) s += R::lam(q, k) * g.x[k][a];
+        xq[a] = s;
+    }
+}
+
+template <int D, int LOAD, int MODE>
+__global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
+{
+    constexpr int NP = D + 1;
+    using R = quad::P1Rule<D>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Lds<D> L(smem, a.nmax, a.smax);
+    const int64_t tile = (MODE == kColoured) ? (int64_t)a.tile_list[blockIdx.x]
+                                             : xcd_block(blockIdx.x, gridDim.x);
+    const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];
+    const int64_t e0 = tile * a.T;
+    const int ne = (int)min((int64_t)a.T, a.E - e0);
+    const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false);
+
+    const bool active = (int)threadIdx.x < ne;
+    double A[NP][NP], bv[NP];
+    int ki[NP], li[NP][NP];
+    int sc = 0;
+    if (active) {
+        const int64_t e = e0 + threadIdx.x;
+        Elem<D> g;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            ki[k] = a.enode[k * a.E + e];
+#pragma unroll
+            for (int d = 0; d < D; ++d) g.x[k][d] = L.xs[d * a.nmax + ki[k]];
+        }
+        elem_geometry<D>(g);
+        const double kv = a.kappa[e] * g.vol, cv = a.c * g.vol;
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int j = i; j < NP; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) s += g.B[i][d] * g.B[j][d];
+                A[i][j] = kv * s + cv * quad::p1_mass<D>(i, j);
+                A[j][i] = A[i][j];
+            }
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const uint64_t r = L.rb[ki[i]];
+            const int base = L.ust[ki[i]];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const int p = a.epos[(i * NP + j) * a.E + e];
+                li[i][j] = base + __popcll(r & ((1ull << p) - 1ull));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i) bv[i] = 0.0;
+        if constexpr (LOAD != FEM_LOAD_NONE) {
+#pragma unroll
+            for (int q = 0; q < R::nq; ++q) {
+                double f;
+                if constexpr (LOAD == FEM_LOAD_SINPROD) {
+                    double xq[D];
+                    qpoint<D>(g, q, xq);
+                    f = 1.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) f *= sinpi(xq[d]);
+                } else {
+                    f = a.fconst;
+                }
+                const double wf = g.vol * R::w(q) * f;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) bv[i] += wf * R::lam(q, i);
+            }
+        }
+        if (MODE == kColoured) sc = a.esub[e];
+    }
+    if (MODE == kAtomic) {
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+#pragma unroll
+                for (int j = 0; j < NP; ++j) atomicAdd(&L.sacc[li[i][j]], A[i][j]);
+                if (LOAD != FEM_LOAD_NONE) atomicAdd(&L.nacc[ki[i]], bv[i]);
+            }
+        }
+    } else {
+        const int nsub = a.tile_nsub[tile];
+        for (int s = 0; s < nsub; ++s) {
+            if (active && sc == s) {
+#pragma unroll
+                for (int i = 0; i < NP; ++i) {
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) L.sacc[li[i][j]] += A[i][j];
+                    if (LOAD != FEM_LOAD_NONE) L.nacc[ki[i]] += bv[i];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < ns; u += blockDim.x) {
+        const int32_t s = L.us[u];
+        const double v = L.sacc[u];
+        if (MODE == kAtomic) unsafeAtomicAdd(a.values + s, v);
+        else if (s < 0) a.values[~s] = v;
+        else a.values[s] += v;
+    }
+    if (LOAD != FEM_LOAD_NONE) {
+        for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+            const int32_t n = L.nd[k];
+            const double v = L.nacc[k];
+            if (MODE == kAtomic) unsafeAtomicAdd(a.rhs + n, v);
+            else if (L.nf[k]) a.rhs[n] = v;
+            else a.rhs[n] += v;
+        }
+    }
+}
+
+// Adjoint: same tile staging; the upstream gradient of every distinct slot is gathered
+// once into LDS; per element dL/dkappa (stored directly) and the vertex gradients
+// (accumulated per tile node in LDS, then one global update per node and axis).
+template <int D, int LOAD, int MODE>
+__global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
+{
+    constexpr int NP = D + 1;
+    using R = quad::P1Rule<D>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Lds<D> L(smem, a.nmax, a.smax);
+    const int64_t tile = (MODE == kColoured) ? (int64_t)a.tile_list[blockIdx.x]
+                                             : xcd_block(blockIdx.x, gridDim.x);
+    const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];
+    const int64_t e0 = tile * a.T;
+    const int ne = (int)min((int64_t)a.T, a.E - e0);
+    stage_tile<D>(a, L, tile, nn, false, true);
+
+    const bool active = (int)threadIdx.x < ne;
+    double xbar[NP][D];
+    int ki[NP];
+    int sc = 0;
+    if (active) {
+        const int64_t e = e0 + threadIdx.x;
+        Elem<D> g;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            ki[k] = a.enode[k * a.E + e];
+#pragma unroll
+            for (int d = 0; d < D; ++d) g.x[k][d] = L.xs[d * a.nmax + ki[k]];
+        }
+        elem_geometry<D>(g);
+        double G[NP][NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const uint64_t r = L.rb[ki[i]];
+            const int base = L.ust[ki[i]];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const int p = a.epos[(i * NP + j) * a.E + e];
+                G[i][j] = L.sacc[base + __popcll(r & ((1ull << p) - 1ull))];
+            }
+        }
+        double s = 0.0, msum = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                double bb = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) bb += g.B[i][d] * g.B[j][d];
+                s += G[i][j] * bb;
+                msum += G[i][j] * quad::p1_mass<D>(i, j);
+            }
+        if (a.gkappa) {
+            const double dk = g.vol * s;
+            if (a.accumulate) a.gkappa[e] += dk;
+            else a.gkappa[e] = dk;
+        }
+        const double kap = a.kappa[e];
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int d = 0; d < D; ++d) xbar[k][d] = 0.0;
+        double lterm = 0.0;
+        if constexpr (LOAD != FEM_LOAD_NONE) {
+            double gb[NP];
+#pragma unroll
+            for (int i = 0; i < NP; ++i) gb[i] = L.gr[ki[i]];
+#pragma unroll
+            for (int q = 0; q < R::nq; ++q) {
+                double p = 0.0;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) p += gb[i] * R::lam(q, i);
+                double f;
+                if constexpr (LOAD == FEM_LOAD_SINPROD) {
+                    double xq[D], sn[D], cs[D];
+                    qpoint<D>(g, q, xq);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) sincospi(xq[d], &sn[d], &cs[d]);
+                    f = 1.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) f *= sn[d];
+                    const double wp = g.vol * R::w(q) * p;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        double df = M_PI * cs[d];
+#pragma unroll
+                        for (int d2 = 0; d2 < D; ++d2)
+                            if (d2 != d) df *= sn[d2];
+#pragma unroll
+                        for (int k = 0; k < NP; ++k) xbar[k][d] += wp * R::lam(q, k) * df;
+                    }
+                } else {
+                    f = a.fconst;
+                }
+                lterm += R::w(q) * p * f;
+            }
+        }
+        double T[D][D];
+#pragma unroll
+        for (int d1 = 0; d1 < D; ++d1)
+#pragma unroll
+            for (int d2 = 0; d2 < D; ++d2) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < NP; ++i)
+#pragma unroll
+                    for (int j = 0; j < NP; ++j)
+                        acc += g.B[i][d1] * (G[i][j] + G[j][i]) * g.B[j][d2];
+                T[d1][d2] = acc;
+            }
+        const double scal = kap * s + a.c * msum + lterm;
+#pragma unroll
+        for (int d1 = 0; d1 < D; ++d1)
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                double jb = 0.0;
+#pragma unroll
+                for (int d2 = 0; d2 < D; ++d2)
+                    jb += ((d1 == d2 ? scal : 0.0) - kap * T[d1][d2]) * g.inv[m][d2];
+                jb *= g.vol;
+                xbar[m + 1][d1] += jb;
+                xbar[0][d1] -= jb;
+            }
+        if (MODE == kColoured) sc = a.esub[e];
+    }
+    if (!a.gcoords) return;  // uniform: no further barriers below when coordinates are not wanted
+    if (MODE == kAtomic) {
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+#pragma unroll
+                for (int d = 0; d < D; ++d) atomicAdd(&L.nacc[d * a.nmax + ki[k]], xbar[k][d]);
+        }
+    } else {
+        const int nsub = a.tile_nsub[tile];
+        for (int s = 0; s < nsub; ++s) {
+            if (active && sc == s) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+#pragma unroll
+                    for (int d = 0; d < D; ++d) L.nacc[d * a.nmax + ki[k]] += xbar[k][d];
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+        const int32_t n = L.nd[k];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            double *dst = a.gcoords + d * a.N + n;
+            const double v = L.nacc[d * a.nmax + k];
+            if (MODE == kAtomic) unsafeAtomicAdd(dst, v);
+            else if (L.nf[k]) *dst = v;
+            else *dst += v;
+        }
+    }
+}
+
+template <int D>
+TileArgs base_args(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef)
+{
+    TileArgs a{};
+    a.coords = m->coords;
+    a.N = m->n_nodes;
+    a.E = m->n_elems;
+    a.T = p->tile;
+    a.rowptr = p->rowptr_n;
+    a.tnode_ptr = p->tnode_ptr;
+    a.tnode = p->tnode;
+    a.trun = p->trun;
+    a.tfirst = p->tfirst;
+    a.trfirst = p->trfirst;
+    a.enode = p->enode;
+    a.epos = p->epos;
+    a.esub = p->esub;
+    a.tile_nsub = p->tile_nsub;
+    a.kappa = coef;
+    a.c = f->reaction;
+    a.fconst = f->load_const[0];
+    a.nmax = p->tile_max_nodes;
+    a.smax = p->tile_max_slots;
+    return a;
+}
+
+template <class K>
+void launch(K kernel, const fem_pattern *p, TileArgs a, bool coloured, size_t lds, hipStream_t s)
+{
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    if (!coloured) {
+        a.tile_list = nullptr;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)p->n_tiles), dim3(p->tile), lds, s, a);
+        return;
+    }
+    for (int c = 0; c < p->n_tile_colours; ++c) {
+        int64_t b = p->tile_colour_ptr[c], n = p->tile_colour_ptr[c + 1] - b;
+        if (n <= 0) continue;
+        a.tile_list = p->tile_perm + b;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)n), dim3(p->tile), lds, s, a);
+    }
+}
+
+template <int D, int LOAD>
+int fwd_d(const fem_pattern *p, TileArgs a, bool coloured, hipStream_t s)
+{
+    size_t lds = lds_bytes<D>(a.nmax, a.smax);
+    if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
+    if (coloured)
+        launch(k_p1_tile_fwd<D, LOAD, kColoured>, p, a, true, lds, s);
+    else
+        launch(k_p1_tile_fwd<D, LOAD, kAtomic>, p, a, false, lds, s);
+    return FEM_OK;
+}
+
+template <int D, int LOAD>
+int bwd_d(const fem_pattern *p, TileArgs a, bool coloured, hipStream_t s)
+{
+    size_t lds = lds_bytes<D>(a.nmax, a.smax);
+    if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
+    if (coloured)
+        launch(k_p1_tile_bwd<D, LOAD, kColoured>, p, a, true, lds, s);
+    else
+        launch(k_p1_tile_bwd<D, LOAD, kAtomic>, p, a, false, lds, s);
+    return FEM_OK;
+}
+
+template <int D>
+int fwd_load(const fem_pattern *p, const TileArgs &a, int load, bool coloured, hipStream_t s)
+{
+    switch (load) {
+    case FEM_LOAD_NONE: return fwd_d<D, FEM_LOAD_NONE>(p, a, coloured, s);
+    case FEM_LOAD_CONST: return fwd_d<D, FEM_LOAD_CONST>(p, a, coloured, s);
+    default: return fwd_d<D, FEM_LOAD_SINPROD>(p, a, coloured, s);
+    }
+}
+
+template <int D>
+int bwd_load(const fem_pattern *p, const TileArgs &a, int load, bool coloured, hipStream_t s)
+{
+    switch (load) {
+    case FEM_LOAD_NONE: return bwd_d<D, FEM_LOAD_NONE>(p, a, coloured, s);
+    case FEM_LOAD_CONST: return bwd_d<D, FEM_LOAD_CONST>(p, a, coloured, s);
+    default: return bwd_d<D, FEM_LOAD_SINPROD>(p, a, coloured, s);
+    }
+}
+
+}  // namespace
+
+int p1_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,
+                    double *values, double *rhs, unsigned flags, hipStream_t s)
+{
+    if (p->n_tiles == 0) return FEM_OK;
+    const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
+    TileArgs a = (m->dim == 2) ? base_args<2>(p, m, f, coef) : base_args<3>(p, m, f, coef);
+    a.values = values;
+    a.rhs = rhs;
+    a.use_first = coloured && !(flags & FEM_ACCUMULATE);
+    const int load = rhs ? f->load : FEM_LOAD_NONE;
+    int rc = (m->dim == 2) ? fwd_load<2>(p, a, load, coloured, s) : fwd_load<3>(p, a, load, coloured, s);
+    if (rc != FEM_OK) return rc;
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+int p1_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
+                     const double *coef, const double *gvalues, const double *grhs,
+                     double *gcoef, double *gcoords, unsigned flags, hipStream_t s)
+{
+    if (p->n_tiles == 0) return FEM_OK;
+    const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
+    TileArgs a = (m->dim == 2) ? base_args<2>(p, m, f, coef) : base_args<3>(p, m, f, coef);
+    a.gvalues = gvalues;
+    a.grhs = grhs;
+    a.gkappa = gcoef;
+    a.gcoords = gcoords;
+    a.accumulate = (flags & FEM_ACCUMULATE) != 0;
+    a.use_first = coloured && !a.accumulate;
+    const int load = grhs ? f->load : FEM_LOAD_NONE;
+    int rc = (m->dim == 2) ? bwd_load<2>(p, a, load, coloured, s) : bwd_load<3>(p, a, load, coloured, s);
+    if (rc != FEM_OK) return rc;
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+}  // namespace fem

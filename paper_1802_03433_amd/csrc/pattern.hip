@@ -383,12 +383,93 @@ int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipS
         hipLaunchKernelGGL(k_slot_map, dim3(grid_for(EK, kThreads)), dim3(kThreads), 0, s, m->conn,
                            E, npe, p->rowptr_n, p->colind_n, p->slot, d_err);
 
-    // 4. colouring
+    // 4. tile plan (LDS-combined scatter); element colouring when tiles do not apply
+    FEM_HIP_TRY(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    {
+        // isolated nodes: rows with no entries (their RHS is never written by a tile)
+        std::vector<int32_t> rp(N + 1);
+        FEM_HIP_TRY(hipMemcpyAsync(rp.data(), p->rowptr_n, sizeof(int32_t) * (N + 1),
+                                   hipMemcpyDeviceToHost, s));
+        FEM_HIP_TRY(hipStreamSynchronize(s));
+        int32_t mr = 0;
+        bool iso = false;
+        for (int64_t i = 0; i < N; ++i) {
+            mr = std::max(mr, rp[i + 1] - rp[i]);
+            iso = iso || (rp[i + 1] == rp[i]);
+        }
+        p->max_row = mr * (int32_t)nc;
+        p->has_isolated_nodes = iso;
+    }
+    if (h_err & kErrSlotMissing) return fail(FEM_ERR_HIP, "internal: slot map lookup failed");
+    int tile = 256;
+    unsigned tsh = (flags >> 8) & 0xfu;
+    if (tsh) tile = 1 << tsh;
+    int rc = FEM_ERR_UNSUPPORTED;
+    if (E > 0) {
+        rc = build_tile_plan(p, m->conn, tile, s);
+        if (rc != FEM_OK && rc != FEM_ERR_UNSUPPORTED) return rc;
+    }
+    if (rc != FEM_OK) {
+        clear_error();
+        FEM_TRY(build_element_colouring(p, m->conn, s));
+    }
+    return FEM_OK;
+}
+
+int jp_rounds_check(int *d_rem, int nrounds, int *d_err, hipStream_t s, bool *done)
+{
+    std::vector<int> h_rem(nrounds);
+    int h_err = 0;
+    FEM_HIP_TRY(hipMemcpyAsync(h_rem.data(), d_rem, sizeof(int) * nrounds, hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    if (h_err & kErrColours) return fail(FEM_ERR_UNSUPPORTED, "colouring needs more than 128 colours");
+    *done = h_rem[nrounds - 1] == 0;
+    return FEM_OK;
+}
+
+int sort_by_colour(const int32_t *colour, int64_t n, int32_t *perm, std::vector<int64_t> &ptr,
+                   hipStream_t s)
+{
+    ptr.assign(1, 0);
+    if (n == 0) return FEM_OK;
+    Tmp tmp(s);
+    const int64_t nblk = (n + kThreads - 1) / kThreads;
+    int32_t *hist = nullptr;
+    int64_t *hoff = nullptr, *cptr = nullptr;
+    FEM_TRY(tmp.get(&hist, (size_t)kMaxColours * nblk));
+    FEM_TRY(tmp.get(&hoff, (size_t)kMaxColours * nblk + 1));
+    FEM_TRY(tmp.get(&cptr, kMaxColours + 1));
+    std::vector<int64_t> h(kMaxColours + 1, 0);
+    hipLaunchKernelGGL(k_colour_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, colour, n, nblk,
+                       hist);
+    FEM_TRY(scan_counts_i64(hist, hoff, (int64_t)kMaxColours * nblk, s));
+    hipLaunchKernelGGL(k_colour_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, colour, n, nblk,
+                       hoff, perm);
+    hipLaunchKernelGGL(k_colour_ptr, dim3(1), dim3(kMaxColours + 1), 0, s, hoff, nblk, cptr);
+    FEM_HIP_TRY(hipMemcpyAsync(h.data(), cptr, sizeof(int64_t) * (kMaxColours + 1),
+                               hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    int ncol = 0;
+    for (int c = 0; c < kMaxColours; ++c)
+        if (h[c + 1] > h[c]) ncol = c + 1;
+    ptr.assign(h.begin(), h.begin() + ncol + 1);
+    return FEM_OK;
+}
+
+int build_element_colouring(fem_pattern *p, const int32_t *conn, hipStream_t s)
+{
+    const int64_t E = p->n_elems;
+    const int npe = p->npe;
+    const int64_t EK = E * npe;
+    Tmp tmp(s);
+    int *d_err = nullptr;
+    FEM_TRY(tmp.get(&d_err, 1));
+    FEM_HIP_TRY(hipMemsetAsync(d_err, 0, sizeof(int), s));
     const int nvert = p->dim + 1;
-    int32_t *cA = nullptr, *cB = nullptr;
+    int32_t *cA = nullptr;
     FEM_TRY(pattern_alloc(p, (void **)&p->colour, sizeof(int32_t) * E));
     FEM_TRY(tmp.get(&cA, E));
-    cB = p->colour;
     if (E > 0)
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(E, kThreads)), dim3(kThreads), 0, s, cA, E,
                            (int32_t)-1);
@@ -396,75 +477,35 @@ int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipS
     int *d_rem = nullptr;
     FEM_TRY(tmp.get(&d_rem, kRoundsPerCheck));
     int rounds = 0;
-    int32_t *cur = cA, *nxt = cB;
+    int32_t *cur = cA, *nxt = p->colour;
     while (E > 0) {
         FEM_HIP_TRY(hipMemsetAsync(d_rem, 0, sizeof(int) * kRoundsPerCheck, s));
         for (int r = 0; r < kRoundsPerCheck; ++r) {
             hipLaunchKernelGGL(k_colour_round, dim3(grid_for(E, kThreads)), dim3(kThreads), 0, s,
-                               cur, nxt, m->conn, E, nvert, p->n2e_ptr, p->n2e, d_rem + r, d_err);
+                               cur, nxt, conn, E, nvert, p->n2e_ptr, p->n2e, d_rem + r, d_err);
             std::swap(cur, nxt);
             ++rounds;
         }
-        int h_rem[kRoundsPerCheck];
-        FEM_HIP_TRY(hipMemcpyAsync(h_rem, d_rem, sizeof(h_rem), hipMemcpyDeviceToHost, s));
-        FEM_TRY(read_err(d_err, s, &h_err));
-        if (h_err & kErrColours)
-            return fail(FEM_ERR_UNSUPPORTED, "element colouring needs more than 128 colours");
-        if (h_rem[kRoundsPerCheck - 1] == 0) break;
+        bool done = false;
+        FEM_TRY(jp_rounds_check(d_rem, kRoundsPerCheck, d_err, s, &done));
+        if (done) break;
         if (rounds > 100000) return fail(FEM_ERR_HIP, "colouring did not terminate");
     }
     if (E > 0 && cur != p->colour)
         FEM_HIP_TRY(hipMemcpyAsync(p->colour, cur, sizeof(int32_t) * E, hipMemcpyDeviceToDevice, s));
-
-    // 5. stable sort by colour
-    const int64_t nblk = (E + kThreads - 1) / kThreads;
-    int32_t *hist = nullptr;
-    int64_t *hoff = nullptr, *cptr = nullptr;
-    FEM_TRY(tmp.get(&hist, (size_t)kMaxColours * nblk));
-    FEM_TRY(tmp.get(&hoff, (size_t)kMaxColours * nblk + 1));
-    FEM_TRY(tmp.get(&cptr, kMaxColours + 1));
     FEM_TRY(pattern_alloc(p, (void **)&p->perm, sizeof(int32_t) * E));
-    std::vector<int64_t> h_cptr(kMaxColours + 1, 0);
-    if (E > 0) {
-        hipLaunchKernelGGL(k_colour_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, p->colour, E,
-                           nblk, hist);
-        FEM_TRY(scan_counts_i64(hist, hoff, (int64_t)kMaxColours * nblk, s));
-        hipLaunchKernelGGL(k_colour_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, p->colour,
-                           E, nblk, hoff, p->perm);
-        hipLaunchKernelGGL(k_colour_ptr, dim3(1), dim3(kMaxColours + 1), 0, s, hoff, nblk, cptr);
-        FEM_HIP_TRY(hipMemcpyAsync(h_cptr.data(), cptr, sizeof(int64_t) * (kMaxColours + 1),
-                                   hipMemcpyDeviceToHost, s));
-    }
-    // 6. colour-ordered copies
+    FEM_TRY(sort_by_colour(p->colour, E, p->perm, p->colour_ptr, s));
+    p->n_colours = (int32_t)p->colour_ptr.size() - 1;
     FEM_TRY(pattern_alloc(p, (void **)&p->conn_perm, sizeof(int32_t) * EK));
     FEM_TRY(pattern_alloc(p, (void **)&p->slot_perm, sizeof(int32_t) * EK * npe));
     if (E > 0) {
-        hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(EK, kThreads)), dim3(kThreads), 0, s,
-                           m->conn, p->perm, p->conn_perm, (int64_t)npe, E);
+        hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(EK, kThreads)), dim3(kThreads), 0, s, conn,
+                           p->perm, p->conn_perm, (int64_t)npe, E);
         hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(EK * npe, kThreads)), dim3(kThreads), 0, s,
                            p->slot, p->perm, p->slot_perm, (int64_t)npe * npe, E);
     }
     FEM_HIP_TRY(hipGetLastError());
-    FEM_TRY(read_err(d_err, s, &h_err));
-    if (h_err & kErrSlotMissing) return fail(FEM_ERR_HIP, "internal: slot map lookup failed");
-
-    int ncol = 0;
-    for (int c = 0; c < kMaxColours; ++c)
-        if (h_cptr[c + 1] > h_cptr[c]) ncol = c + 1;
-    p->n_colours = ncol;
-    p->colour_ptr.assign(h_cptr.begin(), h_cptr.begin() + ncol + 1);
-    (void)rounds;
-
-    // longest dof row (host scan over a small copy is avoided: derive from the node rows)
-    int32_t *h_rp = nullptr;
-    std::vector<int32_t> rp(N + 1);
-    FEM_HIP_TRY(hipMemcpyAsync(rp.data(), p->rowptr_n, sizeof(int32_t) * (N + 1),
-                               hipMemcpyDeviceToHost, s));
-    FEM_HIP_TRY(hipStreamSynchronize(s));
-    (void)h_rp;
-    int32_t mr = 0;
-    for (int64_t i = 0; i < N; ++i) mr = std::max(mr, rp[i + 1] - rp[i]);
-    p->max_row = mr * (int32_t)nc;
+    p->has_element_colouring = true;
     return FEM_OK;
 }
 

@@ -1,0 +1,500 @@
+// Tile plan of the LDS-combined scatter.
+//
+// Alg. 1 of the paper sums each element's contributions in shared memory before the
+// global atomicAdd.  Here the shared-memory stage spans a whole tile: `tile` consecutive
+// elements (one workgroup) add their element matrices into an LDS image of the distinct
+// matrix slots the tile touches, then write each distinct slot to HBM once.  Measured on
+// MI355X, FP64 global atomics on scattered addresses run ~7x slower than on coalesced
+// ones and ~25x slower than coalesced plain read-modify-writes, so the plan lists every
+// tile's distinct slots in ascending order (coalesced updates) and colours the tiles so
+// that the deterministic variant can use plain read-modify-writes.
+//
+// Per tile: its distinct nodes (ascending) and, per node, a 64-bit mask of the row
+// positions the tile writes; the distinct slots are the set bits, node by node, so their
+// order is ascending in the CSR.  Per element: the index of each vertex in the tile's
+// node list (uint16) and, per local pair (i, j), the position of conn_j in the row of
+// conn_i (uint8).  Tile colours: Jones-Plassmann on "tiles sharing a node"; for every
+// slot, the tile of lowest colour writing it stores instead of adding (no zero-fill).
+// Intra-tile colours: greedy in element order, so LDS accumulation in colour phases is
+// deterministic.
+#include <algorithm>
+
+#include "fem_internal.h"
+
+namespace fem {
+
+namespace {
+
+constexpr int kTT = 256;         // threads of the plan-building workgroups
+constexpr int kNodeCap = 2048;   // tile * npe candidates sorted in LDS
+constexpr int kMaxTilesPerNode = 32;
+
+enum : int { kErrPos = 1, kErrTilesPerNode = 2, kErrSub = 4, kErrMissing = 8, kErrColours = 16 };
+
+__device__ __forceinline__ int next_pow2(int c)
+{
+    int P = 1;
+    while (P < c) P <<= 1;
+    return P;
+}
+
+// ascending bitonic sort of sh[0..P), P a power of two, by NT threads
+template <int NT>
+__device__ void block_bitonic(int32_t *sh, int P)
+{
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += NT) {
+                int l = i ^ j;
+                if (l > i) {
+                    int32_t a = sh[i], b = sh[l];
+                    bool ascending = (i & k) == 0;
+                    if ((a > b) == ascending) {
+                        sh[i] = b;
+                        sh[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// exclusive scan over the workgroup (NT threads), LDS Hillis-Steele
+template <int NT>
+__device__ int block_scan_excl(int v, int *sh, int *total)
+{
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+        int add = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int incl = sh[t];
+    *total = sh[NT - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int32_t key)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t prio_hash(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Count (FILL = false) or list (FILL = true) each tile's distinct nodes; when listing,
+// also write enode, epos and the per-node row-position masks.
+template <bool FILL>
+__global__ __launch_bounds__(kTT) void k_tile_nodes(const int32_t *__restrict__ conn, int64_t E,
+                                                    int npe, int T, int32_t *__restrict__ tile_nn,
+                                                    const int32_t *__restrict__ tnode_ptr,
+                                                    int32_t *__restrict__ tnode,
+                                                    uint16_t *__restrict__ enode,
+                                                    const int32_t *__restrict__ slot,
+                                                    const int32_t *__restrict__ rowptr,
+                                                    uint8_t *__restrict__ epos,
+                                                    uint64_t *__restrict__ trun, int *maxes, int *err)
+{
+    __shared__ int32_t sh[kNodeCap];
+    __shared__ int32_t un[kNodeCap];
+    __shared__ unsigned long long rb[kNodeCap];
+    __shared__ int scan_sh[kTT];
+    const int64_t t = blockIdx.x;
+    const int64_t e0 = t * T;
+    const int ne = (int)min((int64_t)T, E - e0);
+    const int cnt = ne * npe;
+    const int P = next_pow2(cnt);
+    for (int i = threadIdx.x; i < P; i += kTT)
+        sh[i] = i < cnt ? conn[(int64_t)(i / ne) * E + e0 + (i % ne)] : INT32_MAX;
+    __syncthreads();
+    block_bitonic<kTT>(sh, P);
+    const int per = (P + kTT - 1) / kTT;
+    const int b0 = min(P, (int)threadIdx.x * per), b1 = min(P, b0 + per);
+    int local = 0;
+    for (int i = b0; i < b1; ++i)
+        local += (sh[i] != INT32_MAX && (i == 0 || sh[i] != sh[i - 1])) ? 1 : 0;
+    int total;
+    int off = block_scan_excl<kTT>(local, scan_sh, &total);
+    if (!FILL) {
+        if (threadIdx.x == 0) {
+            tile_nn[t] = total;
+            atomicMax(&maxes[0], total);
+        }
+        return;
+    }
+    const int32_t base = tnode_ptr[t];
+    for (int i = b0; i < b1; ++i)
+        if (sh[i] != INT32_MAX && (i == 0 || sh[i] != sh[i - 1])) {
+            un[off] = sh[i];
+            tnode[base + off] = sh[i];
+            ++off;
+        }
+    for (int k = threadIdx.x; k < total; k += kTT) rb[k] = 0ull;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < cnt; idx += kTT) {
+        int k = idx / ne, el = idx - k * ne;
+        int64_t e = e0 + el;
+        int32_t node = conn[(int64_t)k * E + e];
+        enode[(int64_t)k * E + e] = (uint16_t)lower_bound_i32(un, total, node);
+    }
+    for (int idx = threadIdx.x; idx < cnt * npe; idx += kTT) {
+        int ij = idx / ne, el = idx - ij * ne;
+        int i = ij / npe;
+        int64_t e = e0 + el;
+        int32_t row = conn[(int64_t)i * E + e];
+        int32_t p = slot[(int64_t)ij * E + e] - rowptr[row];
+        if (p < 0 || p >= kTileMaxRow) {
+            atomicOr(err, kErrPos);
+            p = 0;
+        }
+        epos[(int64_t)ij * E + e] = (uint8_t)p;
+        int li = lower_bound_i32(un, total, row);
+        atomicOr(&rb[li], 1ull << p);
+    }
+    __syncthreads();
+    int slots = 0;
+    for (int k = threadIdx.x; k < total; k += kTT) {
+        trun[base + k] = rb[k];
+        slots += __popcll(rb[k]);
+    }
+    int sum;
+    block_scan_excl<kTT>(slots, scan_sh, &sum);
+    if (threadIdx.x == 0) atomicMax(&maxes[1], sum);
+}
+
+// distinct tiles holding each node (ascending)
+template <bool FILL>
+__global__ void k_node_tiles(const int32_t *__restrict__ n2e_ptr, const int32_t *__restrict__ n2e,
+                             int64_t N, int T, int32_t *__restrict__ cnt,
+                             const int32_t *__restrict__ ptr, int32_t *__restrict__ n2t, int *err)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    int32_t loc[kMaxTilesPerNode];
+    int m = 0;
+    for (int32_t j = n2e_ptr[n]; j < n2e_ptr[n + 1]; ++j) {
+        int32_t tl = n2e[j] / T;
+        int pos = 0;
+        while (pos < m && loc[pos] < tl) ++pos;
+        if (pos < m && loc[pos] == tl) continue;
+        if (m == kMaxTilesPerNode) {
+            atomicOr(err, kErrTilesPerNode);
+            break;
+        }
+        for (int q = m; q > pos; --q) loc[q] = loc[q - 1];
+        loc[pos] = tl;
+        ++m;
+    }
+    if (!FILL) {
+        cnt[n] = m;
+        return;
+    }
+    for (int q = 0; q < m; ++q) n2t[ptr[n] + q] = loc[q];
+}
+
+// One Jones-Plassmann round on the tile graph (tiles adjacent when they share a node).
+__global__ __launch_bounds__(kTT) void k_tile_colour_round(
+    const int32_t *__restrict__ cin, int32_t *__restrict__ cout, const int32_t *__restrict__ tnode_ptr,
+    const int32_t *__restrict__ tnode, const int32_t *__restrict__ n2t_ptr,
+    const int32_t *__restrict__ n2t, int *remaining, int *err)
+{
+    __shared__ int blocked;
+    __shared__ unsigned long long m0, m1;
+    const int32_t t = blockIdx.x;
+    const int32_t c = cin[t];
+    if (c >= 0) {
+        if (threadIdx.x == 0) cout[t] = c;
+        return;
+    }
+    if (threadIdx.x == 0) {
+        blocked = 0;
+        m0 = 0ull;
+        m1 = 0ull;
+    }
+    __syncthreads();
+    const uint32_t p = prio_hash((uint32_t)t);
+    unsigned long long l0 = 0, l1 = 0;
+    int bl = 0;
+    for (int32_t k = tnode_ptr[t] + threadIdx.x; k < tnode_ptr[t + 1]; k += kTT) {
+        int32_t n = tnode[k];
+        for (int32_t j = n2t_ptr[n]; j < n2t_ptr[n + 1]; ++j) {
+            int32_t t2 = n2t[j];
+            if (t2 == t) continue;
+            int32_t c2 = cin[t2];
+            if (c2 < 0) {
+                uint32_t p2 = prio_hash((uint32_t)t2);
+                if (p2 > p || (p2 == p && t2 > t)) bl = 1;
+            } else if (c2 < 64) {
+                l0 |= 1ull << c2;
+            } else {
+                l1 |= 1ull << (c2 - 64);
+            }
+        }
+    }
+    if (bl) atomicOr(&blocked, 1);
+    if (l0) atomicOr(&m0, l0);
+    if (l1) atomicOr(&m1, l1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (blocked) {
+            cout[t] = -1;
+            atomicAdd(remaining, 1);
+        } else {
+            int col;
+            if (~m0) col = __builtin_ctzll(~m0);
+            else if (~m1) col = 64 + __builtin_ctzll(~m1);
+            else {
+                atomicOr(err, kErrColours);
+                col = kMaxColours - 1;
+            }
+            cout[t] = col;
+        }
+    }
+}
+
+__global__ void k_fill_i32_t(int32_t *p, int64_t n, int32_t v)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+// For every tile node: which of the tile's slots (and the node's RHS entry) no tile of
+// lower colour writes.
+__global__ __launch_bounds__(kTT) void k_tile_first(const int32_t *__restrict__ tcol,
+                                                    const int32_t *__restrict__ tnode_ptr,
+                                                    const int32_t *__restrict__ tnode,
+                                                    const uint64_t *__restrict__ trun,
+                                                    const int32_t *__restrict__ n2t_ptr,
+                                                    const int32_t *__restrict__ n2t,
+                                                    uint64_t *__restrict__ tfirst,
+                                                    uint8_t *__restrict__ trfirst, int *err)
+{
+    const int32_t t = blockIdx.x;
+    const int32_t c = tcol[t];
+    for (int32_t k = tnode_ptr[t] + threadIdx.x; k < tnode_ptr[t + 1]; k += kTT) {
+        int32_t n = tnode[k];
+        uint64_t fb = trun[k];
+        uint8_t rf = 1;
+        for (int32_t j = n2t_ptr[n]; j < n2t_ptr[n + 1]; ++j) {
+            int32_t t2 = n2t[j];
+            if (t2 == t || tcol[t2] > c) continue;
+            rf = 0;
+            int32_t lo = tnode_ptr[t2], cntn = tnode_ptr[t2 + 1] - lo;
+            int k2 = lower_bound_i32(tnode + lo, cntn, n);
+            if (k2 >= cntn || tnode[lo + k2] != n) {
+                atomicOr(err, kErrMissing);
+                continue;
+            }
+            fb &= ~trun[lo + k2];
+        }
+        tfirst[k] = fb;
+        trfirst[k] = rf;
+    }
+}
+
+// Greedy colouring of the elements inside each tile, in element order.
+__global__ __launch_bounds__(kTT) void k_tile_subcolour(const uint16_t *__restrict__ enode, int npe,
+                                                        int64_t E, int T,
+                                                        const int32_t *__restrict__ tnode_ptr,
+                                                        uint8_t *__restrict__ esub,
+                                                        int32_t *__restrict__ nsub, int *err)
+{
+    __shared__ unsigned long long mask[kNodeCap];
+    __shared__ uint16_t en[kNodeCap];
+    __shared__ uint8_t sc[kNodeCap];
+    const int64_t t = blockIdx.x;
+    const int64_t e0 = t * T;
+    const int ne = (int)min((int64_t)T, E - e0);
+    const int nn = tnode_ptr[t + 1] - tnode_ptr[t];
+    for (int k = threadIdx.x; k < nn; k += kTT) mask[k] = 0ull;
+    for (int idx = threadIdx.x; idx < ne * npe; idx += kTT) {
+        int k = idx / ne, el = idx - k * ne;
+        en[el * npe + k] = enode[(int64_t)k * E + e0 + el];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int maxc = 0;
+        for (int el = 0; el < ne; ++el) {
+            unsigned long long m = 0ull;
+            for (int k = 0; k < npe; ++k) m |= mask[en[el * npe + k]];
+            int col;
+            if (~m) col = __builtin_ctzll(~m);
+            else {
+                atomicOr(err, kErrSub);
+                col = kMaxSubColours - 1;
+            }
+            sc[el] = (uint8_t)col;
+            for (int k = 0; k < npe; ++k) mask[en[el * npe + k]] |= 1ull << col;
+            maxc = max(maxc, col + 1);
+        }
+        nsub[t] = maxc;
+    }
+    __syncthreads();
+    for (int el = threadIdx.x; el < ne; el += kTT) esub[e0 + el] = sc[el];
+}
+
+__global__ void k_i64_to_i32_t(const int64_t *__restrict__ in, int32_t *__restrict__ out, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (int32_t)in[t];
+}
+
+struct TmpT {
+    std::vector<void *> ptrs;
+    hipStream_t s;
+    explicit TmpT(hipStream_t st) : s(st) {}
+    template <class T>
+    int get(T **p, size_t count)
+    {
+        void *q = nullptr;
+        hipError_t e = hipMallocAsync(&q, count ? count * sizeof(T) : 8, s);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? FEM_ERR_OOM : FEM_ERR_HIP,
+                        std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        ptrs.push_back(q);
+        *p = (T *)q;
+        return FEM_OK;
+    }
+    ~TmpT()
+    {
+        for (void *q : ptrs) hipFreeAsync(q, s);
+    }
+};
+
+int scan_to_i32(TmpT &tmp, const int32_t *cnt, int64_t n, int32_t *out, int64_t *total,
+                hipStream_t s)
+{
+    int64_t *off = nullptr;
+    FEM_TRY(tmp.get(&off, n + 1));
+    FEM_TRY(scan_counts_i64(cnt, off, n, s));
+    FEM_HIP_TRY(hipMemcpyAsync(total, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    if (*total > INT32_MAX) return fail(FEM_ERR_INDEX_OVERFLOW, "tile plan too large for int32");
+    hipLaunchKernelGGL(k_i64_to_i32_t, dim3(grid_for(n + 1, kTT)), dim3(kTT), 0, s, off, out, n + 1);
+    return FEM_OK;
+}
+
+}  // namespace
+
+int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
+{
+    const int npe = p->npe;
+    const int64_t E = p->n_elems, N = p->n_nodes;
+    if (p->order != 1 || p->ncomp != 1)
+        return fail(FEM_ERR_UNSUPPORTED, "tile plan: P1 scalar patterns only");
+    if (p->max_row > kTileMaxRow) return fail(FEM_ERR_UNSUPPORTED, "tile plan: row longer than 64");
+    if (T < 64 || T > 1024 || (T & (T - 1)) || T * npe > kNodeCap)
+        return fail(FEM_ERR_UNSUPPORTED, "tile plan: tile size out of range");
+    const int64_t nt = (E + T - 1) / T;
+    p->tile = T;
+    p->n_tiles = nt;
+    TmpT tmp(s);
+    int *d_err = nullptr, *d_max = nullptr;
+    FEM_TRY(tmp.get(&d_err, 1));
+    FEM_TRY(tmp.get(&d_max, 2));
+    FEM_HIP_TRY(hipMemsetAsync(d_err, 0, sizeof(int), s));
+    FEM_HIP_TRY(hipMemsetAsync(d_max, 0, 2 * sizeof(int), s));
+
+    // tile nodes
+    int32_t *tile_nn = nullptr;
+    FEM_TRY(tmp.get(&tile_nn, nt));
+    hipLaunchKernelGGL((k_tile_nodes<false>), dim3((unsigned)nt), dim3(kTT), 0, s, conn, E, npe, T,
+                       tile_nn, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, d_max,
+                       d_err);
+    FEM_TRY(pattern_alloc(p, (void **)&p->tnode_ptr, sizeof(int32_t) * (nt + 1)));
+    int64_t n_tn = 0;
+    FEM_TRY(scan_to_i32(tmp, tile_nn, nt, p->tnode_ptr, &n_tn, s));
+    FEM_TRY(pattern_alloc(p, (void **)&p->tnode, sizeof(int32_t) * n_tn));
+    FEM_TRY(pattern_alloc(p, (void **)&p->trun, sizeof(uint64_t) * n_tn));
+    FEM_TRY(pattern_alloc(p, (void **)&p->tfirst, sizeof(uint64_t) * n_tn));
+    FEM_TRY(pattern_alloc(p, (void **)&p->trfirst, sizeof(uint8_t) * n_tn));
+    FEM_TRY(pattern_alloc(p, (void **)&p->enode, sizeof(uint16_t) * E * npe));
+    FEM_TRY(pattern_alloc(p, (void **)&p->epos, sizeof(uint8_t) * E * npe * npe));
+    hipLaunchKernelGGL((k_tile_nodes<true>), dim3((unsigned)nt), dim3(kTT), 0, s, conn, E, npe, T,
+                       nullptr, p->tnode_ptr, p->tnode, p->enode, p->slot, p->rowptr_n, p->epos,
+                       p->trun, d_max, d_err);
+
+    // node -> tiles
+    int32_t *n2t_cnt = nullptr, *n2t_ptr = nullptr, *n2t = nullptr;
+    FEM_TRY(tmp.get(&n2t_cnt, N));
+    FEM_TRY(tmp.get(&n2t_ptr, N + 1));
+    hipLaunchKernelGGL((k_node_tiles<false>), dim3(grid_for(N, kTT)), dim3(kTT), 0, s, p->n2e_ptr,
+                       p->n2e, N, T, n2t_cnt, nullptr, nullptr, d_err);
+    int64_t n_n2t = 0;
+    FEM_TRY(scan_to_i32(tmp, n2t_cnt, N, n2t_ptr, &n_n2t, s));
+    FEM_TRY(tmp.get(&n2t, n_n2t));
+    hipLaunchKernelGGL((k_node_tiles<true>), dim3(grid_for(N, kTT)), dim3(kTT), 0, s, p->n2e_ptr,
+                       p->n2e, N, T, nullptr, n2t_ptr, n2t, d_err);
+    int h_err = 0, h_max[2] = {0, 0};
+    FEM_HIP_TRY(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipMemcpyAsync(h_max, d_max, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    if (h_err & kErrPos) return fail(FEM_ERR_UNSUPPORTED, "tile plan: row position beyond 64");
+    if (h_err & kErrTilesPerNode)
+        return fail(FEM_ERR_UNSUPPORTED, "tile plan: a node lies in more than 32 tiles");
+    p->tile_max_nodes = h_max[0];
+    p->tile_max_slots = h_max[1];
+
+    // tile colouring
+    FEM_TRY(pattern_alloc(p, (void **)&p->tile_colour, sizeof(int32_t) * nt));
+    int32_t *cA = nullptr;
+    FEM_TRY(tmp.get(&cA, nt));
+    hipLaunchKernelGGL(k_fill_i32_t, dim3(grid_for(nt, kTT)), dim3(kTT), 0, s, cA, nt, (int32_t)-1);
+    constexpr int kRounds = 4;
+    int *d_rem = nullptr;
+    FEM_TRY(tmp.get(&d_rem, kRounds));
+    int32_t *cur = cA, *nxt = p->tile_colour;
+    for (int rounds = 0;; rounds += kRounds) {
+        FEM_HIP_TRY(hipMemsetAsync(d_rem, 0, sizeof(int) * kRounds, s));
+        for (int r = 0; r < kRounds; ++r) {
+            hipLaunchKernelGGL(k_tile_colour_round, dim3((unsigned)nt), dim3(kTT), 0, s, cur, nxt,
+                               p->tnode_ptr, p->tnode, n2t_ptr, n2t, d_rem + r, d_err);
+            std::swap(cur, nxt);
+        }
+        bool done = false;
+        FEM_TRY(jp_rounds_check(d_rem, kRounds, d_err, s, &done));
+        if (done) break;
+        if (rounds > 100000) return fail(FEM_ERR_HIP, "tile colouring did not terminate");
+    }
+    if (cur != p->tile_colour)
+        FEM_HIP_TRY(hipMemcpyAsync(p->tile_colour, cur, sizeof(int32_t) * nt,
+                                   hipMemcpyDeviceToDevice, s));
+    FEM_TRY(pattern_alloc(p, (void **)&p->tile_perm, sizeof(int32_t) * nt));
+    FEM_TRY(sort_by_colour(p->tile_colour, nt, p->tile_perm, p->tile_colour_ptr, s));
+    p->n_tile_colours = (int32_t)p->tile_colour_ptr.size() - 1;
+
+    // first writers, intra-tile colours
+    hipLaunchKernelGGL(k_tile_first, dim3((unsigned)nt), dim3(kTT), 0, s, p->tile_colour,
+                       p->tnode_ptr, p->tnode, p->trun, n2t_ptr, n2t, p->tfirst, p->trfirst, d_err);
+    FEM_TRY(pattern_alloc(p, (void **)&p->esub, sizeof(uint8_t) * E));
+    FEM_TRY(pattern_alloc(p, (void **)&p->tile_nsub, sizeof(int32_t) * nt));
+    hipLaunchKernelGGL(k_tile_subcolour, dim3((unsigned)nt), dim3(kTT), 0, s, p->enode, npe, E, T,
+                       p->tnode_ptr, p->esub, p->tile_nsub, d_err);
+    FEM_HIP_TRY(hipGetLastError());
+    FEM_HIP_TRY(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    if (h_err & kErrMissing) return fail(FEM_ERR_HIP, "internal: tile node lookup failed");
+    if (h_err & kErrSub) return fail(FEM_ERR_UNSUPPORTED, "tile plan: more than 64 colours in a tile");
+    p->has_tiles = true;
+    return FEM_OK;
+}
+
+}  // namespace fem

@@ -80,12 +80,91 @@ def test_pattern_bit_exact_full_size():
 
 
 def _check_colouring(m, pat):
+    """Elements given the same colour (scatter order) never share a node."""
     col = _np(pat.colours())
-    assert col.min() >= 0 and col.max() == pat.n_colours - 1
-    for c in range(pat.n_colours):
+    assert col.min() >= 0
+    for c in np.unique(col):
         nodes = m.conn[:, col == c].ravel()
         assert np.unique(nodes).size == nodes.size, f"colour {c} has elements sharing a node"
     return col
+
+
+def _fan_mesh(k=70, seed=3):
+    """A 2D fan: k triangles around one centre node, whose row holds k+1 > 64 entries
+    (beyond the tile plan), plus an isolated node."""
+    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+    r = 1.0 + 0.1 * np.random.default_rng(seed).random(k)
+    coords = np.concatenate([[[0.0], [0.0]], np.stack([r * np.cos(ang), r * np.sin(ang)]),
+                             [[5.0], [5.0]]], axis=1)
+    conn = np.stack([np.zeros(k), 1 + np.arange(k), 1 + (np.arange(k) + 1) % k]).astype(np.int32)
+    return meshgen.Mesh(2, 1, 1, np.ascontiguousarray(coords), np.ascontiguousarray(conn))
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "coloured"])
+def test_long_rows_fall_back_to_element_scatter(scatter):
+    m = _fan_mesh()
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    assert pat.max_row == m.n_elems + 1
+    _check_colouring(m, pat)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=9)
+    form = F.Form("helmholtz", "sinprod")
+    v, r = F.assemble(pat, d, form, torch.from_numpy(kappa).cuda(), scatter=scatter)
+    rp, ci = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
+    assert scaled_close(_np(v), ov, oav, RTOL)[0]
+    assert scaled_close(_np(r), orhs, oar, RTOL)[0]
+    assert _np(r)[-1] == 0.0  # isolated node
+
+
+@pytest.mark.parametrize("tile", [64, 128, 512, 1024])
+@pytest.mark.parametrize("scatter", ["atomic", "coloured"])
+def test_tile_sizes(tile, scatter):
+    m = MESHES["tet12"]()
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d, tile=tile)
+    _check_colouring(m, pat)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=10)
+    G, g = meshgen.upstream_grads(pat.nnz, pat.n_rows, seed=10)
+    form = F.Form("helmholtz", "sinprod")
+    kap = torch.from_numpy(kappa).cuda()
+    v, r = F.assemble(pat, d, form, kap, scatter=scatter)
+    gk, gx = F.assemble_backward(pat, d, form, kap, torch.from_numpy(G).cuda(),
+                                 torch.from_numpy(g).cuda(), scatter=scatter)
+    rp, ci = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
+    assert scaled_close(_np(v), ov, oav, RTOL)[0]
+    assert scaled_close(_np(r), orhs, oar, RTOL)[0]
+    dk, adk, dx, adx = oracle.backward_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci, G, g)
+    assert scaled_close(_np(gk)[0], dk, adk, RTOL)[0]
+    assert scaled_close(_np(gx), dx, adx, RTOL)[0]
+
+
+@pytest.mark.parametrize("name", ["tri32", "tet12"])
+def test_element_scatter_reference_path(name):
+    """The per-element scatter (no tile combining) agrees with the oracle too."""
+    m = MESHES[name]()
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=12)
+    G, g = meshgen.upstream_grads(pat.nnz, pat.n_rows, seed=12)
+    form = F.Form("helmholtz", "sinprod")
+    kap = torch.from_numpy(kappa).cuda()
+    v, r = F.assemble(pat, d, form, kap, element_scatter=True)
+    gk, gx = F.assemble_backward(pat, d, form, kap, torch.from_numpy(G).cuda(),
+                                 torch.from_numpy(g).cuda(), element_scatter=True)
+    rp, ci = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
+    assert scaled_close(_np(v), ov, oav, RTOL)[0]
+    assert scaled_close(_np(r), orhs, oar, RTOL)[0]
+    dk, adk, dx, adx = oracle.backward_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci, G, g)
+    assert scaled_close(_np(gk)[0], dk, adk, RTOL)[0]
+    assert scaled_close(_np(gx), dx, adx, RTOL)[0]
+    with pytest.raises(F.FemError):
+        F.assemble(pat, d, form, kap, scatter="coloured", element_scatter=True)
 
 
 @pytest.mark.parametrize("name", ["tri32", "tet12"])
@@ -271,7 +350,7 @@ def test_empty_mesh():
     conn = torch.zeros(4, 0, dtype=torch.int32, device=dev)
     d = F.Mesh(coords, conn)
     pat = F.Pattern(d)
-    assert pat.nnz == 0 and pat.n_colours == 0
+    assert pat.nnz == 0
     v, r = F.assemble(pat, d, F.Form("helmholtz", "const", load_const=(1.0,)),
                       torch.zeros(1, 0, dtype=torch.float64, device=dev))
     assert v.numel() == 0 and float(r.abs().sum()) == 0.0
