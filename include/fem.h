@@ -69,6 +69,9 @@ extern "C" {
                                      bitwise reproducible run to run */
 #define FEM_ACCUMULATE 0x2u       /* add into the outputs instead of overwriting them */
 #define FEM_VALIDATE 0x4u         /* device-side input checks (synchronises) */
+#define FEM_PREC_FP32 0x8u        /* elasticity: element-matrix contraction on FP32 matrix
+                                     cores (inputs rounded to FP32, FP32 accumulation);
+                                     the scatter and the outputs stay FP64 */
 #define FEM_ELEMENT_SCATTER 0x10u /* scatter each element straight to HBM, without the
                                      workgroup (tile) combining stage; a reference path
                                      for comparisons (atomic only unless the pattern has

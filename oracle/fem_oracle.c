@@ -804,6 +804,15 @@ int fo_assemble_p2_elasticity(int64_t n_nodes, int64_t n_elems, const double *co
             for (int a = 0; a < 3; ++a) x[k][a] = coords[a * n_nodes + v[k]];
         double vol = p2_gram_real(x, G);
         p2_split_real(G, Kl, Km);
+        /* Entry magnitude for the comparison tolerance: the element's largest entry, added
+         * to every slot the element touches.  Entries such as the a != b couplings cancel
+         * inside the element (exactly zero on undistorted elements), so their own size
+         * says nothing about the rounding they carry; the element's scale does. */
+        double emax = 0.0;
+        for (int r = 0; r < 900; ++r) {
+            double val = fabs(lam[e] * Kl[r] + mu[e] * Km[r]);
+            if (val > emax) emax = val;
+        }
         for (int i = 0; i < 10; ++i)
             for (int a = 0; a < 3; ++a) {
                 int64_t row = 3 * (int64_t)v[i] + a;
@@ -814,7 +823,7 @@ int fo_assemble_p2_elasticity(int64_t n_nodes, int64_t n_elems, const double *co
                         int64_t slot = find_slot(rowptr, colind, row, (int32_t)(3 * v[j] + b));
                         if (slot < 0) return FO_ERR_NOTFOUND;
                         if (values) values[slot] += val;
-                        if (abs_values) abs_values[slot] += fabs(val);
+                        if (abs_values) abs_values[slot] += emax;
                     }
                 if (load == LOAD_CONST) {
                     double bv = body_force[a] * vol * PHI_MEAN[i];

@@ -30,6 +30,7 @@ SCATTER_COLOURED = 0x1
 ACCUMULATE = 0x2
 VALIDATE = 0x4
 ELEMENT_SCATTER = 0x10
+PREC_FP32 = 0x8
 
 
 def TILE_LOG2(k: int) -> int:

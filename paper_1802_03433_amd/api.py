@@ -36,7 +36,8 @@ def _need(t: torch.Tensor, dtype, name: str):
         raise ValueError(f"{name} must be contiguous")
 
 
-def _flags(scatter: str, accumulate: bool, validate: bool, element_scatter: bool = False) -> int:
+def _flags(scatter: str, accumulate: bool, validate: bool, element_scatter: bool = False,
+           fp32: bool = False) -> int:
     if scatter not in _SCATTER:
         raise ValueError(f"scatter must be one of {list(_SCATTER)}")
     f = _SCATTER[scatter]
@@ -46,6 +47,8 @@ def _flags(scatter: str, accumulate: bool, validate: bool, element_scatter: bool
         f |= L.VALIDATE
     if element_scatter:
         f |= L.ELEMENT_SCATTER
+    if fp32:
+        f |= L.PREC_FP32
     return f
 
 
@@ -164,9 +167,10 @@ class Pattern:
 def assemble(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tensor,
              values: torch.Tensor | None = None, rhs: torch.Tensor | None = None,
              scatter: str = "atomic", accumulate: bool = False, validate: bool = False,
-             element_scatter: bool = False):
+             element_scatter: bool = False, fp32: bool = False):
     """fem_assemble; returns (values [nnz], rhs [n_rows] or None).
-    element_scatter: bypass the tile combining stage (reference path)."""
+    element_scatter: bypass the tile combining stage (reference path).
+    fp32: elasticity element matrices on FP32 matrix cores (outputs stay FP64)."""
     _need(coef, torch.float64, "coef")
     dev = mesh.coords.device
     if values is None:
@@ -179,7 +183,7 @@ def assemble(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tensor,
     ms, fs = mesh.cstruct(), form.cstruct()
     rc = L.lib.fem_assemble(pattern.handle, ctypes.byref(ms), ctypes.byref(fs), _ptr(coef),
                             _ptr(values), _ptr(rhs),
-                            _flags(scatter, accumulate, validate, element_scatter),
+                            _flags(scatter, accumulate, validate, element_scatter, fp32),
                             _stream_ptr(dev))
     L.check(rc, "fem_assemble")
     return values, rhs

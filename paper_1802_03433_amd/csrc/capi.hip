@@ -56,7 +56,9 @@ int check_form(const fem_pattern *p, const fem_form *f)
                         "elasticity is provided for P2 tetrahedra with a 3-component pattern");
         if (f->load == FEM_LOAD_SINPROD)
             return fail(FEM_ERR_UNSUPPORTED, "elasticity takes no sin-product load");
-        return fail(FEM_ERR_UNSUPPORTED, "elasticity kernel not available in this build");
+        if (!p->has_tiles)
+            return fail(FEM_ERR_UNSUPPORTED, "elasticity needs the tile plan (rows of at most 128 nodes)");
+        return FEM_OK;
     }
     return fail(FEM_ERR_INVALID_ARG, "unknown form kind");
 }
@@ -227,7 +229,8 @@ int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *for
     FEM_TRY(check_mesh(mesh, true));
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));
-    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER))
+    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER |
+                  FEM_PREC_FP32))
         return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
     if (!values && p->nnz > 0) return fail(FEM_ERR_INVALID_ARG, "values is NULL");
     if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
@@ -238,6 +241,11 @@ int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *for
     const bool accumulate = (flags & FEM_ACCUMULATE) != 0;
     double *rhs_ok = (form->load == FEM_LOAD_NONE) ? nullptr : rhs;
     if (flags & FEM_VALIDATE) FEM_TRY(validate_elements(mesh, s));
+    const bool elast = form->kind == FEM_FORM_ELASTICITY;
+    if (elast && (flags & FEM_ELEMENT_SCATTER))
+        return fail(FEM_ERR_UNSUPPORTED, "elasticity is assembled through the tile plan only");
+    if (!elast && (flags & FEM_PREC_FP32))
+        return fail(FEM_ERR_UNSUPPORTED, "FEM_PREC_FP32 applies to elasticity only");
     const bool tiles = p->has_tiles && !(flags & FEM_ELEMENT_SCATTER);
     if (!tiles && coloured && !p->has_element_colouring)
         return fail(FEM_ERR_UNSUPPORTED, "per-element coloured scatter needs an element colouring");
@@ -248,6 +256,7 @@ int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *for
         if (rhs_ok && (!(tiles && coloured) || p->has_isolated_nodes))
             FEM_TRY(fill_zero_f64(rhs_ok, p->n_rows, s));
     }
+    if (elast) return p2_tile_forward(p, mesh, form, coef, values, rhs_ok, flags, s);
     if (tiles) return p1_tile_forward(p, mesh, form, coef, values, rhs_ok, flags, s);
     return p1_forward(p, mesh, form, coef, values, rhs_ok, flags & ~FEM_VALIDATE, s);
 }
@@ -260,20 +269,28 @@ int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_
     FEM_TRY(check_mesh(mesh, true));
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));
-    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER))
+    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER |
+                  FEM_PREC_FP32))
         return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
     if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
     hipStream_t s = (hipStream_t)stream;
     const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
     const bool accumulate = (flags & FEM_ACCUMULATE) != 0;
+    const bool elast = form->kind == FEM_FORM_ELASTICITY;
+    if (flags & FEM_PREC_FP32) return fail(FEM_ERR_UNSUPPORTED, "the adjoint is FP64 only");
+    if (elast && (flags & FEM_ELEMENT_SCATTER))
+        return fail(FEM_ERR_UNSUPPORTED, "elasticity is assembled through the tile plan only");
     if (flags & FEM_VALIDATE) FEM_TRY(validate_elements(mesh, s));
     const bool tiles = p->has_tiles && !(flags & FEM_ELEMENT_SCATTER);
     if (!tiles && coloured && !p->has_element_colouring)
         return fail(FEM_ERR_UNSUPPORTED, "per-element coloured scatter needs an element colouring");
-    if (!accumulate && grad_coords && (!(tiles && coloured) || p->has_isolated_nodes))
+    if (!accumulate && grad_coords && (!(tiles && coloured) || p->has_isolated_nodes || elast))
         FEM_TRY(fill_zero_f64(grad_coords, p->dim * p->n_nodes, s));
     if (!grad_coef && !grad_coords) return FEM_OK;
     const double *grhs = (form->load == FEM_LOAD_NONE) ? nullptr : grad_rhs;
+    if (elast)
+        return p2_tile_backward(p, mesh, form, coef, grad_values, grhs, grad_coef, grad_coords,
+                                flags, s);
     if (tiles)
         return p1_tile_backward(p, mesh, form, coef, grad_values, grhs, grad_coef, grad_coords,
                                 flags, s);

@@ -94,12 +94,16 @@ struct fem_pattern {
     int32_t tile_max_slots = 0;    // largest distinct-slot count of a tile
     int32_t *tnode_ptr = nullptr;  // [n_tiles+1] offsets into tnode
     int32_t *tnode = nullptr;      // distinct nodes of each tile, ascending
-    uint64_t *trun = nullptr;      // per tile node: bit p set <=> the tile writes row position p
+    uint64_t *trun = nullptr;      // per tile node (tile_mw words): bit p <=> the tile writes
+                                   // row position p
     uint64_t *tfirst = nullptr;    // per tile node: bits of trun this tile writes first
                                    // (lowest tile colour among the tiles writing the slot)
     uint8_t *trfirst = nullptr;    // per tile node: 1 if this tile writes the node's RHS first
-    uint16_t *enode = nullptr;     // [npe][E] index of conn(e,k) in its tile's node list
-    uint8_t *epos = nullptr;       // [npe*npe][E] position of conn(e,j) in the row of conn(e,i)
+    int32_t tile_mw = 1;           // 64-bit mask words per tile node (P1: 1, P2: 2)
+    uint16_t *enode16 = nullptr;   // P2: [npe][E] index of conn(e,k) in its tile's node list
+    uint8_t *epos8 = nullptr;      // P2: [npe*npe][E] position of conn(e,j) in the row of conn(e,i)
+    uint64_t *enode = nullptr;     // [E] 16-bit field k: index of conn(e,k) in its tile's node list
+    uint32_t *epos = nullptr;      // [npe][E] byte j: position of conn(e,j) in the row of conn(e,i)
     uint8_t *esub = nullptr;       // [E] colour of the element inside its tile
     int32_t *tile_nsub = nullptr;  // [n_tiles] number of intra-tile colours
     int32_t *tile_colour = nullptr;  // [n_tiles]
@@ -130,6 +134,13 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int tile, hipStream_t s
 int sort_by_colour(const int32_t *colour, int64_t n, int32_t *perm, std::vector<int64_t> &ptr,
                    hipStream_t s);
 int jp_rounds_check(int *d_rem, int nrounds, int *d_err, hipStream_t s, bool *done);
+
+// P2 elasticity (p2.hip)
+int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,
+                    double *values, double *rhs, unsigned flags, hipStream_t s);
+int p2_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
+                     const double *coef, const double *gvalues, const double *grhs,
+                     double *gcoef, double *gcoords, unsigned flags, hipStream_t s);
 
 // tile-combined P1 launchers (p1_tile.hip)
 int p1_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,

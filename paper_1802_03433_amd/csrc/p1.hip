@@ -106,7 +106,7 @@ __device__ __forceinline__ void sinprod(const double *xq, double &f)
 {
     f = 1.0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) f *= sinpi(xq[a]);
+    for (int a = 0; a < D; ++a) f *= fem_sinpi(xq[a]);
 }
 
 template <int D>
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_p1_bwd(P1BwdArgs b)
                 double xq[D], sn[D], cs[D];
                 quad_point<D>(g, q, xq);
 #pragma unroll
-                for (int d = 0; d < D; ++d) sincospi(xq[d], &sn[d], &cs[d]);
+                for (int d = 0; d < D; ++d) fem_sincospi(xq[d], &sn[d], &cs[d]);
                 f = 1.0;
 #pragma unroll
                 for (int d = 0; d < D; ++d) f *= sn[d];

@@ -31,8 +31,8 @@ struct TileArgs {
     const uint64_t *trun;
     const uint64_t *tfirst;
     const uint8_t *trfirst;
-    const uint16_t *enode;
-    const uint8_t *epos;
+    const uint64_t *enode;
+    const uint32_t *epos;
     const uint8_t *esub;
     const int32_t *tile_nsub;
     const int32_t *tile_list;  // coloured: tiles of the launched colour
@@ -83,21 +83,28 @@ size_t lds_bytes(int nmax, int smax)
            sizeof(int32_t) * (size_t)(nmax + smax + nmax + 1024) + (size_t)nmax + 16;
 }
 
+// Exclusive scan over the workgroup: shuffle scan inside each wavefront, wave totals
+// through LDS (blockDim is a multiple of 64).
 __device__ int wg_scan_excl(int v, int *sh, int *total)
 {
-    const int t = threadIdx.x, n = blockDim.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < n; off <<= 1) {
-        int add = (t >= off) ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
-    int incl = sh[t];
-    *total = sh[n - 1];
+    if (lane == 63) sh[w] = x;
     __syncthreads();
-    return incl - v;
+    int base = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        int t = sh[i];
+        base += (i < w) ? t : 0;
+        tot += t;
+    }
+    *total = tot;
+    __syncthreads();
+    return base + x - v;
 }
 
 // Phase A.  Returns the number of distinct slots of the tile.
@@ -238,23 +245,34 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
     const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];
     const int64_t e0 = tile * a.T;
     const int ne = (int)min((int64_t)a.T, a.E - e0);
-    const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false);
-
+    // element data first: its latency overlaps the staging of the tile
     const bool active = (int)threadIdx.x < ne;
-    double A[NP][NP], bv[NP];
-    int ki[NP], li[NP][NP];
+    const int64_t e = e0 + threadIdx.x;
+    uint64_t en = 0;
+    uint32_t pr[NP];
+    double kap = 0.0;
     int sc = 0;
     if (active) {
-        const int64_t e = e0 + threadIdx.x;
+        en = a.enode[e];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) pr[i] = a.epos[i * a.E + e];
+        kap = a.kappa[e];
+        if (MODE == kColoured) sc = a.esub[e];
+    }
+    const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false);
+
+    double A[NP][NP], bv[NP];
+    int ki[NP], li[NP][NP];
+    if (active) {
         Elem<D> g;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            ki[k] = a.enode[k * a.E + e];
+            ki[k] = (int)((en >> (16 * k)) & 0xffffu);
 #pragma unroll
             for (int d = 0; d < D; ++d) g.x[k][d] = L.xs[d * a.nmax + ki[k]];
         }
         elem_geometry<D>(g);
-        const double kv = a.kappa[e] * g.vol, cv = a.c * g.vol;
+        const double kv = kap * g.vol, cv = a.c * g.vol;
 #pragma unroll
         for (int i = 0; i < NP; ++i)
 #pragma unroll
@@ -271,7 +289,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
             const int base = L.ust[ki[i]];
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
-                const int p = a.epos[(i * NP + j) * a.E + e];
+                const int p = (int)((pr[i] >> (8 * j)) & 0xffu);
                 li[i][j] = base + __popcll(r & ((1ull << p) - 1ull));
             }
         }
@@ -286,7 +304,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
                     qpoint<D>(g, q, xq);
                     f = 1.0;
 #pragma unroll
-                    for (int d = 0; d < D; ++d) f *= sinpi(xq[d]);
+                    for (int d = 0; d < D; ++d) f *= fem_sinpi(xq[d]);
                 } else {
                     f = a.fconst;
                 }
@@ -295,7 +313,6 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
                 for (int i = 0; i < NP; ++i) bv[i] += wf * R::lam(q, i);
             }
         }
-        if (MODE == kColoured) sc = a.esub[e];
     }
     if (MODE == kAtomic) {
         if (active) {
@@ -354,18 +371,28 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
     const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];
     const int64_t e0 = tile * a.T;
     const int ne = (int)min((int64_t)a.T, a.E - e0);
-    stage_tile<D>(a, L, tile, nn, false, true);
-
     const bool active = (int)threadIdx.x < ne;
-    double xbar[NP][D];
-    int ki[NP];
+    const int64_t e = e0 + threadIdx.x;
+    uint64_t en = 0;
+    uint32_t pr[NP];
+    double kap = 0.0;
     int sc = 0;
     if (active) {
-        const int64_t e = e0 + threadIdx.x;
+        en = a.enode[e];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) pr[i] = a.epos[i * a.E + e];
+        kap = a.kappa[e];
+        if (MODE == kColoured) sc = a.esub[e];
+    }
+    stage_tile<D>(a, L, tile, nn, false, true);
+
+    double xbar[NP][D];
+    int ki[NP];
+    if (active) {
         Elem<D> g;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            ki[k] = a.enode[k * a.E + e];
+            ki[k] = (int)((en >> (16 * k)) & 0xffffu);
 #pragma unroll
             for (int d = 0; d < D; ++d) g.x[k][d] = L.xs[d * a.nmax + ki[k]];
         }
@@ -377,7 +404,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
             const int base = L.ust[ki[i]];
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
-                const int p = a.epos[(i * NP + j) * a.E + e];
+                const int p = (int)((pr[i] >> (8 * j)) & 0xffu);
                 G[i][j] = L.sacc[base + __popcll(r & ((1ull << p) - 1ull))];
             }
         }
@@ -397,7 +424,6 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
             if (a.accumulate) a.gkappa[e] += dk;
             else a.gkappa[e] = dk;
         }
-        const double kap = a.kappa[e];
 #pragma unroll
         for (int k = 0; k < NP; ++k)
 #pragma unroll
@@ -417,7 +443,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
                     double xq[D], sn[D], cs[D];
                     qpoint<D>(g, q, xq);
 #pragma unroll
-                    for (int d = 0; d < D; ++d) sincospi(xq[d], &sn[d], &cs[d]);
+                    for (int d = 0; d < D; ++d) fem_sincospi(xq[d], &sn[d], &cs[d]);
                     f = 1.0;
 #pragma unroll
                     for (int d = 0; d < D; ++d) f *= sn[d];
@@ -463,7 +489,6 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
                 xbar[m + 1][d1] += jb;
                 xbar[0][d1] -= jb;
             }
-        if (MODE == kColoured) sc = a.esub[e];
     }
     if (!a.gcoords) return;  // uniform: no further barriers below when coordinates are not wanted
     if (MODE == kAtomic) {

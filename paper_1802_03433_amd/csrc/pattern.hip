@@ -401,7 +401,8 @@ int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipS
         p->has_isolated_nodes = iso;
     }
     if (h_err & kErrSlotMissing) return fail(FEM_ERR_HIP, "internal: slot map lookup failed");
-    int tile = 256;
+    // default tile: 256 P1 elements (one per thread); 8 P2 elements (two per wavefront)
+    int tile = (p->order == 1) ? 256 : 8;
     unsigned tsh = (flags >> 8) & 0xfu;
     if (tsh) tile = 1 << tsh;
     int rc = FEM_ERR_UNSUPPORTED;

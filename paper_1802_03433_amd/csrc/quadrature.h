@@ -77,3 +77,61 @@ struct Tet14 {
 
 }  // namespace quad
 }  // namespace fem
+
+namespace fem {
+
+// ---- sin(pi x), cos(pi x) for the sin-product load -----------------------------------
+// Written from the mathematics: x = 2k + r with r = x - 2 rint(x/2) in [-1, 1] (exact in
+// binary floating point), folded to t in [-1/2, 1/2] by sin(pi r) = sin(pi (+-1 - r))
+// (also exact), then the Taylor series sin(pi t) = sum_k (-1)^k (pi t)^(2k+1) / (2k+1)!
+// truncated after degree 21 (remainder below 2e-18 on |t| <= 1/2), evaluated by Horner in
+// t^2.  cos(pi r) = sin(pi (1/2 - |r|)).
+namespace sinpi_detail {
+constexpr double kPi = 3.14159265358979323846;
+constexpr double coef(int k)  // (-1)^k pi^(2k+1) / (2k+1)!
+{
+    double c = kPi;
+    for (int i = 1; i <= k; ++i) c *= -(kPi * kPi) / double((2 * i) * (2 * i + 1));
+    return c;
+}
+__device__ __forceinline__ double core(double t)  // sin(pi t), |t| <= 1/2
+{
+    const double t2 = t * t;
+    double p = coef(10);
+    p = fma(p, t2, coef(9));
+    p = fma(p, t2, coef(8));
+    p = fma(p, t2, coef(7));
+    p = fma(p, t2, coef(6));
+    p = fma(p, t2, coef(5));
+    p = fma(p, t2, coef(4));
+    p = fma(p, t2, coef(3));
+    p = fma(p, t2, coef(2));
+    p = fma(p, t2, coef(1));
+    p = fma(p, t2, coef(0));
+    return t * p;
+}
+__device__ __forceinline__ double reduce(double x)  // r in [-1, 1], x - r an even integer
+{
+    return x - 2.0 * rint(0.5 * x);
+}
+__device__ __forceinline__ double fold(double r)  // t in [-1/2, 1/2], sin(pi t) = sin(pi r)
+{
+    return r > 0.5 ? 1.0 - r : (r < -0.5 ? -1.0 - r : r);
+}
+}  // namespace sinpi_detail
+
+__device__ __forceinline__ double fem_sinpi(double x)
+{
+    using namespace sinpi_detail;
+    return core(fold(reduce(x)));
+}
+
+__device__ __forceinline__ void fem_sincospi(double x, double *s, double *c)
+{
+    using namespace sinpi_detail;
+    const double r = reduce(x);
+    *s = core(fold(r));
+    *c = core(0.5 - fabs(r));
+}
+
+}  // namespace fem

@@ -101,21 +101,24 @@ __device__ __forceinline__ uint32_t prio_hash(uint32_t x)
 }
 
 // Count (FILL = false) or list (FILL = true) each tile's distinct nodes; when listing,
-// also write enode, epos and the per-node row-position masks.
-template <bool FILL>
+// also write the per-element node indices and row positions and the per-node masks of
+// row positions (MW 64-bit words per node).  PACKED (P1): node indices as four 16-bit
+// fields of one uint64 per element, positions as four bytes of one uint32 per element
+// row.  Otherwise (P2): node indices uint16 [npe][E], positions uint8 [npe*npe][E].
+template <bool FILL, int MW, bool PACKED>
 __global__ __launch_bounds__(kTT) void k_tile_nodes(const int32_t *__restrict__ conn, int64_t E,
                                                     int npe, int T, int32_t *__restrict__ tile_nn,
                                                     const int32_t *__restrict__ tnode_ptr,
                                                     int32_t *__restrict__ tnode,
-                                                    uint16_t *__restrict__ enode,
+                                                    void *__restrict__ enode_v,
                                                     const int32_t *__restrict__ slot,
                                                     const int32_t *__restrict__ rowptr,
-                                                    uint8_t *__restrict__ epos,
+                                                    void *__restrict__ epos_v,
                                                     uint64_t *__restrict__ trun, int *maxes, int *err)
 {
     __shared__ int32_t sh[kNodeCap];
     __shared__ int32_t un[kNodeCap];
-    __shared__ unsigned long long rb[kNodeCap];
+    __shared__ unsigned long long rb[kNodeCap * MW];
     __shared__ int scan_sh[kTT];
     const int64_t t = blockIdx.x;
     const int64_t e0 = t * T;
@@ -147,32 +150,35 @@ __global__ __launch_bounds__(kTT) void k_tile_nodes(const int32_t *__restrict__ 
             tnode[base + off] = sh[i];
             ++off;
         }
-    for (int k = threadIdx.x; k < total; k += kTT) rb[k] = 0ull;
+    for (int k = threadIdx.x; k < total * MW; k += kTT) rb[k] = 0ull;
     __syncthreads();
     for (int idx = threadIdx.x; idx < cnt; idx += kTT) {
         int k = idx / ne, el = idx - k * ne;
         int64_t e = e0 + el;
         int32_t node = conn[(int64_t)k * E + e];
-        enode[(int64_t)k * E + e] = (uint16_t)lower_bound_i32(un, total, node);
+        uint16_t li = (uint16_t)lower_bound_i32(un, total, node);
+        if (PACKED) reinterpret_cast<uint16_t *>((uint64_t *)enode_v + e)[k] = li;
+        else ((uint16_t *)enode_v)[(int64_t)k * E + e] = li;
     }
     for (int idx = threadIdx.x; idx < cnt * npe; idx += kTT) {
         int ij = idx / ne, el = idx - ij * ne;
-        int i = ij / npe;
+        int i = ij / npe, j = ij - i * npe;
         int64_t e = e0 + el;
         int32_t row = conn[(int64_t)i * E + e];
         int32_t p = slot[(int64_t)ij * E + e] - rowptr[row];
-        if (p < 0 || p >= kTileMaxRow) {
+        if (p < 0 || p >= 64 * MW) {
             atomicOr(err, kErrPos);
             p = 0;
         }
-        epos[(int64_t)ij * E + e] = (uint8_t)p;
+        if (PACKED) reinterpret_cast<uint8_t *>((uint32_t *)epos_v + (int64_t)i * E + e)[j] = (uint8_t)p;
+        else ((uint8_t *)epos_v)[(int64_t)ij * E + e] = (uint8_t)p;
         int li = lower_bound_i32(un, total, row);
-        atomicOr(&rb[li], 1ull << p);
+        atomicOr(&rb[li * MW + (p >> 6)], 1ull << (p & 63));
     }
     __syncthreads();
     int slots = 0;
-    for (int k = threadIdx.x; k < total; k += kTT) {
-        trun[base + k] = rb[k];
+    for (int k = threadIdx.x; k < total * MW; k += kTT) {
+        trun[(int64_t)base * MW + k] = rb[k];
         slots += __popcll(rb[k]);
     }
     int sum;
@@ -278,6 +284,7 @@ __global__ void k_fill_i32_t(int32_t *p, int64_t n, int32_t v)
 
 // For every tile node: which of the tile's slots (and the node's RHS entry) no tile of
 // lower colour writes.
+template <int MW>
 __global__ __launch_bounds__(kTT) void k_tile_first(const int32_t *__restrict__ tcol,
                                                     const int32_t *__restrict__ tnode_ptr,
                                                     const int32_t *__restrict__ tnode,
@@ -291,7 +298,8 @@ __global__ __launch_bounds__(kTT) void k_tile_first(const int32_t *__restrict__ 
     const int32_t c = tcol[t];
     for (int32_t k = tnode_ptr[t] + threadIdx.x; k < tnode_ptr[t + 1]; k += kTT) {
         int32_t n = tnode[k];
-        uint64_t fb = trun[k];
+        uint64_t fb[MW];
+        for (int w = 0; w < MW; ++w) fb[w] = trun[(int64_t)k * MW + w];
         uint8_t rf = 1;
         for (int32_t j = n2t_ptr[n]; j < n2t_ptr[n + 1]; ++j) {
             int32_t t2 = n2t[j];
@@ -303,15 +311,16 @@ __global__ __launch_bounds__(kTT) void k_tile_first(const int32_t *__restrict__ 
                 atomicOr(err, kErrMissing);
                 continue;
             }
-            fb &= ~trun[lo + k2];
+            for (int w = 0; w < MW; ++w) fb[w] &= ~trun[(int64_t)(lo + k2) * MW + w];
         }
-        tfirst[k] = fb;
+        for (int w = 0; w < MW; ++w) tfirst[(int64_t)k * MW + w] = fb[w];
         trfirst[k] = rf;
     }
 }
 
 // Greedy colouring of the elements inside each tile, in element order.
-__global__ __launch_bounds__(kTT) void k_tile_subcolour(const uint16_t *__restrict__ enode, int npe,
+template <bool PACKED>
+__global__ __launch_bounds__(kTT) void k_tile_subcolour(const void *__restrict__ enode_v, int npe,
                                                         int64_t E, int T,
                                                         const int32_t *__restrict__ tnode_ptr,
                                                         uint8_t *__restrict__ esub,
@@ -327,7 +336,8 @@ __global__ __launch_bounds__(kTT) void k_tile_subcolour(const uint16_t *__restri
     for (int k = threadIdx.x; k < nn; k += kTT) mask[k] = 0ull;
     for (int idx = threadIdx.x; idx < ne * npe; idx += kTT) {
         int k = idx / ne, el = idx - k * ne;
-        en[el * npe + k] = enode[(int64_t)k * E + e0 + el];
+        en[el * npe + k] = PACKED ? (uint16_t)(((const uint64_t *)enode_v)[e0 + el] >> (16 * k))
+                                  : ((const uint16_t *)enode_v)[(int64_t)k * E + e0 + el];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -398,11 +408,17 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
 {
     const int npe = p->npe;
     const int64_t E = p->n_elems, N = p->n_nodes;
-    if (p->order != 1 || p->ncomp != 1)
-        return fail(FEM_ERR_UNSUPPORTED, "tile plan: P1 scalar patterns only");
-    if (p->max_row > kTileMaxRow) return fail(FEM_ERR_UNSUPPORTED, "tile plan: row longer than 64");
-    if (T < 64 || T > 1024 || (T & (T - 1)) || T * npe > kNodeCap)
+    // P1: one mask word per node (rows up to 64 nodes), packed element indices;
+    // P2: two mask words (rows up to 128 nodes), structure-of-arrays element indices
+    const bool packed = (p->order == 1);
+    const int MW = packed ? 1 : 2;
+    const int node_row = p->max_row / p->ncomp;
+    if (node_row > 64 * MW)
+        return fail(FEM_ERR_UNSUPPORTED, "tile plan: row longer than the position masks");
+    if (packed && (T < 64 || T > 1024 || (T & (T - 1))))
         return fail(FEM_ERR_UNSUPPORTED, "tile plan: tile size out of range");
+    if (T < 1 || T * npe > kNodeCap) return fail(FEM_ERR_UNSUPPORTED, "tile plan: tile too large");
+    p->tile_mw = MW;
     const int64_t nt = (E + T - 1) / T;
     p->tile = T;
     p->n_tiles = nt;
@@ -416,21 +432,35 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
     // tile nodes
     int32_t *tile_nn = nullptr;
     FEM_TRY(tmp.get(&tile_nn, nt));
-    hipLaunchKernelGGL((k_tile_nodes<false>), dim3((unsigned)nt), dim3(kTT), 0, s, conn, E, npe, T,
-                       tile_nn, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, d_max,
-                       d_err);
+    if (packed)
+        hipLaunchKernelGGL((k_tile_nodes<false, 1, true>), dim3((unsigned)nt), dim3(kTT), 0, s, conn,
+                           E, npe, T, tile_nn, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, d_max, d_err);
+    else
+        hipLaunchKernelGGL((k_tile_nodes<false, 2, false>), dim3((unsigned)nt), dim3(kTT), 0, s, conn,
+                           E, npe, T, tile_nn, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, d_max, d_err);
     FEM_TRY(pattern_alloc(p, (void **)&p->tnode_ptr, sizeof(int32_t) * (nt + 1)));
     int64_t n_tn = 0;
     FEM_TRY(scan_to_i32(tmp, tile_nn, nt, p->tnode_ptr, &n_tn, s));
     FEM_TRY(pattern_alloc(p, (void **)&p->tnode, sizeof(int32_t) * n_tn));
-    FEM_TRY(pattern_alloc(p, (void **)&p->trun, sizeof(uint64_t) * n_tn));
-    FEM_TRY(pattern_alloc(p, (void **)&p->tfirst, sizeof(uint64_t) * n_tn));
+    FEM_TRY(pattern_alloc(p, (void **)&p->trun, sizeof(uint64_t) * n_tn * MW));
+    FEM_TRY(pattern_alloc(p, (void **)&p->tfirst, sizeof(uint64_t) * n_tn * MW));
     FEM_TRY(pattern_alloc(p, (void **)&p->trfirst, sizeof(uint8_t) * n_tn));
-    FEM_TRY(pattern_alloc(p, (void **)&p->enode, sizeof(uint16_t) * E * npe));
-    FEM_TRY(pattern_alloc(p, (void **)&p->epos, sizeof(uint8_t) * E * npe * npe));
-    hipLaunchKernelGGL((k_tile_nodes<true>), dim3((unsigned)nt), dim3(kTT), 0, s, conn, E, npe, T,
-                       nullptr, p->tnode_ptr, p->tnode, p->enode, p->slot, p->rowptr_n, p->epos,
-                       p->trun, d_max, d_err);
+    if (packed) {
+        if (npe > 4) return fail(FEM_ERR_UNSUPPORTED, "tile plan: at most 4 nodes per element");
+        FEM_TRY(pattern_alloc(p, (void **)&p->enode, sizeof(uint64_t) * E));
+        FEM_TRY(pattern_alloc(p, (void **)&p->epos, sizeof(uint32_t) * E * npe));
+        hipLaunchKernelGGL((k_tile_nodes<true, 1, true>), dim3((unsigned)nt), dim3(kTT), 0, s, conn,
+                           E, npe, T, nullptr, p->tnode_ptr, p->tnode, (void *)p->enode, p->slot,
+                           p->rowptr_n, (void *)p->epos, p->trun, d_max, d_err);
+    } else {
+        FEM_TRY(pattern_alloc(p, (void **)&p->enode16, sizeof(uint16_t) * E * npe));
+        FEM_TRY(pattern_alloc(p, (void **)&p->epos8, sizeof(uint8_t) * E * npe * npe));
+        hipLaunchKernelGGL((k_tile_nodes<true, 2, false>), dim3((unsigned)nt), dim3(kTT), 0, s, conn,
+                           E, npe, T, nullptr, p->tnode_ptr, p->tnode, (void *)p->enode16, p->slot,
+                           p->rowptr_n, (void *)p->epos8, p->trun, d_max, d_err);
+    }
 
     // node -> tiles
     int32_t *n2t_cnt = nullptr, *n2t_ptr = nullptr, *n2t = nullptr;
@@ -447,7 +477,7 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
     FEM_HIP_TRY(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
     FEM_HIP_TRY(hipMemcpyAsync(h_max, d_max, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     FEM_HIP_TRY(hipStreamSynchronize(s));
-    if (h_err & kErrPos) return fail(FEM_ERR_UNSUPPORTED, "tile plan: row position beyond 64");
+    if (h_err & kErrPos) return fail(FEM_ERR_UNSUPPORTED, "tile plan: row position beyond the masks");
     if (h_err & kErrTilesPerNode)
         return fail(FEM_ERR_UNSUPPORTED, "tile plan: a node lies in more than 32 tiles");
     p->tile_max_nodes = h_max[0];
@@ -482,12 +512,21 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
     p->n_tile_colours = (int32_t)p->tile_colour_ptr.size() - 1;
 
     // first writers, intra-tile colours
-    hipLaunchKernelGGL(k_tile_first, dim3((unsigned)nt), dim3(kTT), 0, s, p->tile_colour,
-                       p->tnode_ptr, p->tnode, p->trun, n2t_ptr, n2t, p->tfirst, p->trfirst, d_err);
+    if (MW == 1)
+        hipLaunchKernelGGL(k_tile_first<1>, dim3((unsigned)nt), dim3(kTT), 0, s, p->tile_colour,
+                           p->tnode_ptr, p->tnode, p->trun, n2t_ptr, n2t, p->tfirst, p->trfirst, d_err);
+    else
+        hipLaunchKernelGGL(k_tile_first<2>, dim3((unsigned)nt), dim3(kTT), 0, s, p->tile_colour,
+                           p->tnode_ptr, p->tnode, p->trun, n2t_ptr, n2t, p->tfirst, p->trfirst, d_err);
     FEM_TRY(pattern_alloc(p, (void **)&p->esub, sizeof(uint8_t) * E));
     FEM_TRY(pattern_alloc(p, (void **)&p->tile_nsub, sizeof(int32_t) * nt));
-    hipLaunchKernelGGL(k_tile_subcolour, dim3((unsigned)nt), dim3(kTT), 0, s, p->enode, npe, E, T,
-                       p->tnode_ptr, p->esub, p->tile_nsub, d_err);
+    if (packed)
+        hipLaunchKernelGGL(k_tile_subcolour<true>, dim3((unsigned)nt), dim3(kTT), 0, s,
+                           (const void *)p->enode, npe, E, T, p->tnode_ptr, p->esub, p->tile_nsub, d_err);
+    else
+        hipLaunchKernelGGL(k_tile_subcolour<false>, dim3((unsigned)nt), dim3(kTT), 0, s,
+                           (const void *)p->enode16, npe, E, T, p->tnode_ptr, p->esub, p->tile_nsub,
+                           d_err);
     FEM_HIP_TRY(hipGetLastError());
     FEM_HIP_TRY(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
     FEM_HIP_TRY(hipStreamSynchronize(s));
