@@ -55,6 +55,43 @@ def _time_calls(torch, fn, reps):
     return a.elapsed_time(b) / reps
 
 
+def _bench_p2(torch, fem, meshgen, dev, steps):
+    """40^3 x 6 P2 tetrahedra, isotropic elasticity, body force (0,0,-1), 14-point rule."""
+    m = meshgen.cube_tet(40, 2, seed=0)
+    coef = torch.from_numpy(meshgen.coefficients(m.n_elems, "elasticity", seed=0)).to(dev)
+    dm = fem.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev), 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pat = fem.Pattern(dm, ncomp=3)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    form = fem.Form("elasticity", "const", load_const=(0.0, 0.0, -1.0))
+    values = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    rhs = torch.empty(pat.n_rows, dtype=torch.float64, device=dev)
+    E = m.n_elems
+    # matrix-core work per element: 4 output tiles x 4 steps of v_mfma_f64_16x16x4
+    # (2 * 16 * 16 * 4 flops each); useful part: 30 x 30 x 14 multiply-adds
+    mfma_flops = 16 * 2 * 16 * 16 * 4
+    useful_flops = 2 * 30 * 30 * 14
+    # bytes: node-pair slot positions (100 B) + node indices (20 B) + lam, mu (16 B) per
+    # element, vertex coordinates, values written once, RHS once
+    alg = E * (100 + 20 + 16) + m.n_nodes * 24 + pat.nnz * 8 + pat.n_rows * 8
+    out = {"workload": "3D cube 40^3 x 6 P2 tets, isotropic elasticity, body force, 14-point rule",
+           "n_elems": E, "nnz": pat.nnz, "pattern_build_ms": build_ms, "n_tile_colours": pat.n_colours}
+    for name, kw in (("atomic_f64", {}), ("coloured_f64", {"scatter": "coloured"}),
+                     ("atomic_f32mfma", {"fp32": True})):
+        def step():
+            fem.assemble(pat, dm, form, coef, values, rhs, **kw)
+        step()
+        ms = _time_calls(torch, step, steps)
+        out[name] = {"ms": ms, "elements_per_s": E / (ms * 1e-3),
+                     "alg_GBps": alg / (ms * 1e-3) / 1e9,
+                     "mfma_util": E * mfma_flops / (ms * 1e-3) / (157.3e12 if "f32" in name else 78.6e12),
+                     "useful_tflops": E * useful_flops / (ms * 1e-3) / 1e12}
+    pat.close()
+    return out
+
+
 def _cpu_baseline(m, kappa, budget_s=12.0):
     import oracle
 
@@ -189,6 +226,7 @@ def main():
         extra["bwd_ms"] = bwd_ms
         extra["bwd_over_fwd"] = bwd_ms / ms_per_step
         extra["bwd_alg_GBps"] = _alg_bytes_bwd(E, N, nnz) / (bwd_ms * 1e-3) / 1e9
+        extra["p2_elasticity"] = _bench_p2(torch, fem, meshgen, dev, max(5, args.steps // 3))
         out["extra"] = extra
 
     if not args.no_cpu_baseline:
