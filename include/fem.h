@@ -76,6 +76,10 @@ extern "C" {
                                      workgroup (tile) combining stage; a reference path
                                      for comparisons (atomic only unless the pattern has
                                      an element colouring) */
+#define FEM_COLOUR_LAUNCHES 0x20u /* coloured scatter as one launch per tile colour
+                                     (reference for comparisons); by default the coloured
+                                     scatter is one launch in which every tile waits for its
+                                     lower-colour neighbours -- same sums, same bits */
 /* fem_build_pattern: elements per tile of the combined scatter, as log2 in bits 8..11
    (0 = default 256; accepted 64..1024) */
 #define FEM_TILE_LOG2(k) (((unsigned)(k) & 0xfu) << 8)

@@ -31,6 +31,7 @@ ACCUMULATE = 0x2
 VALIDATE = 0x4
 ELEMENT_SCATTER = 0x10
 PREC_FP32 = 0x8
+COLOUR_LAUNCHES = 0x20
 
 
 def TILE_LOG2(k: int) -> int:

@@ -14,7 +14,10 @@ import torch
 
 from . import _lib as L
 
-_SCATTER = {"atomic": L.SCATTER_ATOMIC, "coloured": L.SCATTER_COLOURED}
+# "coloured": one launch, tiles in colour order; "coloured-launches": one launch per colour
+# (reference; the same sums in the same order, hence the same bits)
+_SCATTER = {"atomic": L.SCATTER_ATOMIC, "coloured": L.SCATTER_COLOURED,
+            "coloured-launches": L.SCATTER_COLOURED | L.COLOUR_LAUNCHES}
 
 
 def _stream_ptr(device) -> ctypes.c_void_p:

@@ -29,6 +29,9 @@ CFLAGS = [
     "-fPIC",
     # device FP64 atomic adds as hardware instructions (no compare-and-swap loops)
     "-munsafe-fp-atomics",
+    # fuse a*b+c only inside one source expression: the rounding of every kernel
+    # instantiation (atomic, coloured, ordered) is then the same, whatever its control flow
+    "-ffp-contract=on",
     # no packed FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

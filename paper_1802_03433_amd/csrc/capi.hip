@@ -230,7 +230,7 @@ int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *for
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));
     if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER |
-                  FEM_PREC_FP32))
+                  FEM_PREC_FP32 | FEM_COLOUR_LAUNCHES))
         return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
     if (!values && p->nnz > 0) return fail(FEM_ERR_INVALID_ARG, "values is NULL");
     if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
@@ -270,7 +270,7 @@ int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));
     if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER |
-                  FEM_PREC_FP32))
+                  FEM_PREC_FP32 | FEM_COLOUR_LAUNCHES))
         return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
     if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
     hipStream_t s = (hipStream_t)stream;

@@ -56,6 +56,20 @@ int fill_zero_f64(double *p, int64_t n, hipStream_t s)
     return FEM_OK;
 }
 
+__global__ void k_fill_zero_i32(int32_t *__restrict__ p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+int fill_zero_i32(int32_t *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return FEM_OK;
+    hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
 // ---------------------------------------------------------------------------------------
 // exclusive scan of int32 counts -> int64 offsets (three passes: tile sums, scan of the
 // tile sums by one workgroup, tile-local scans plus the tile offset)

@@ -100,8 +100,8 @@ struct fem_pattern {
                                    // (lowest tile colour among the tiles writing the slot)
     uint8_t *trfirst = nullptr;    // per tile node: 1 if this tile writes the node's RHS first
     int32_t tile_mw = 1;           // 64-bit mask words per tile node (P1: 1, P2: 2)
-    uint16_t *enode16 = nullptr;   // P2: [npe][E] index of conn(e,k) in its tile's node list
-    uint8_t *epos8 = nullptr;      // P2: [npe*npe][E] position of conn(e,j) in the row of conn(e,i)
+    uint16_t *enode16 = nullptr;   // P2: [E][npe] index of conn(e,k) in its tile's node list
+    uint8_t *epos8 = nullptr;      // P2: [E][npe*npe] position of conn(e,j) in the row of conn(e,i)
     uint64_t *enode = nullptr;     // [E] 16-bit field k: index of conn(e,k) in its tile's node list
     uint32_t *epos = nullptr;      // [npe][E] byte j: position of conn(e,j) in the row of conn(e,i)
     uint8_t *esub = nullptr;       // [E] colour of the element inside its tile
@@ -110,6 +110,12 @@ struct fem_pattern {
     int32_t *tile_perm = nullptr;    // [n_tiles] tiles sorted by colour
     int32_t n_tile_colours = 0;
     std::vector<int64_t> tile_colour_ptr;  // host [n_tile_colours+1]
+    // ordered single-launch coloured scatter: per tile, the neighbour tiles (sharing a
+    // node) of lower colour it must wait for; control words [n_tiles + 2] (done flags,
+    // ticket counter, spin-limit flag), cleared before each launch
+    int32_t *tpred_ptr = nullptr;  // [n_tiles+1]
+    int32_t *tpred = nullptr;
+    int32_t *tctrl = nullptr;
     std::vector<fem::DevBuf> owned;
     int64_t device_bytes = 0;
 };
@@ -122,8 +128,9 @@ int pattern_alloc(fem_pattern *p, void **ptr, size_t bytes);
 // exclusive scan of n int32 counts into out[0..n] (out[n] = total), int64 accumulation
 int scan_counts_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
 
-// fill kernel (graph-capture safe alternative to hipMemsetAsync)
+// fill kernels (graph-capture safe alternative to hipMemsetAsync)
 int fill_zero_f64(double *p, int64_t n, hipStream_t s);
+int fill_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 
 // pattern construction (pattern.hip)
 int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipStream_t s);
@@ -181,6 +188,81 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks)
     int64_t q = nblocks / kXcd, r = nblocks % kXcd;
     int64_t x = b % kXcd, k = b / kXcd;
     return x * q + (x < r ? x : r) + k;
+}
+
+// ---- ordered single-launch coloured scatter (shared by the P1 and P2 kernels) ----------
+// Tiles are taken in colour order through a ticket counter, so every lower-colour
+// neighbour a tile waits for has already started.  Writes to the outputs use agent-scope
+// (cross-XCD coherent) loads and stores; a tile publishes its done flag after its stores
+// have completed.  The spin is bounded: past the limit the tile records the failure in
+// ctrl[n_tiles + 1] and goes on (wrong sums, never a hang).
+constexpr int kSpinLimit = 1 << 22;
+
+__device__ __forceinline__ double ld_coherent(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// thread 0 takes the next ticket; every thread returns it
+__device__ __forceinline__ int64_t take_ticket(int32_t *ctrl, int64_t n_tiles, int *sh)
+{
+    if (threadIdx.x == 0) *sh = atomicAdd(ctrl + n_tiles, 1);
+    __syncthreads();
+    return *sh;
+}
+
+__device__ __forceinline__ void wait_preds(const int32_t *pred_ptr, const int32_t *pred,
+                                           int32_t *ctrl, int64_t n_tiles, int64_t tile)
+{
+    for (int32_t k = pred_ptr[tile] + threadIdx.x; k < pred_ptr[tile + 1]; k += blockDim.x) {
+        int32_t *flag = ctrl + pred[k];
+        int spins = 0;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if (++spins > kSpinLimit) {
+                atomicOr(ctrl + n_tiles + 1, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+}
+
+// out[slot(u)] = first(u) ? val(u) : out[slot(u)] + val(u) for u < n, coherent accesses;
+// the loads of CH updates are issued before any of their stores, so a workgroup waits
+// for one memory round trip per CH updates instead of one per update.
+template <int CH, class SlotF, class ValF, class FirstF>
+__device__ __forceinline__ void ordered_rmw(double *out, int n, SlotF slot, ValF val, FirstF first)
+{
+    const int bd = blockDim.x;
+    for (int u0 = threadIdx.x; u0 < n; u0 += CH * bd) {
+        double old[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int u = u0 + c * bd;
+            old[c] = (u < n && !first(u)) ? ld_coherent(out + slot(u)) : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int u = u0 + c * bd;
+            // a first writer stores its value as is (0.0 + v would turn -0.0 into +0.0)
+            if (u < n) st_coherent(out + slot(u), first(u) ? val(u) : old[c] + val(u));
+        }
+    }
+}
+
+__device__ __forceinline__ void publish_done(int32_t *ctrl, int64_t tile)
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);  // this lane's coherent stores have completed
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(ctrl + tile, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace fem

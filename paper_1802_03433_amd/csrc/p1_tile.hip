@@ -19,7 +19,10 @@ namespace fem {
 
 namespace {
 
-enum Mode : int { kAtomic = 0, kColoured = 1 };
+// kAtomic: device-scope FP64 atomics.  kColoured: one launch per tile colour, plain
+// read-modify-writes.  kOrdered: one launch, tiles in colour order waiting for their
+// lower-colour neighbours, coherent read-modify-writes (same sums as kColoured).
+enum Mode : int { kAtomic = 0, kColoured = 1, kOrdered = 2 };
 
 struct TileArgs {
     const double *coords;
@@ -35,7 +38,10 @@ struct TileArgs {
     const uint32_t *epos;
     const uint8_t *esub;
     const int32_t *tile_nsub;
-    const int32_t *tile_list;  // coloured: tiles of the launched colour
+    const int32_t *tile_list;  // coloured: tiles of the launched colour; ordered: all, by colour
+    const int32_t *pred_ptr, *pred;
+    int32_t *ctrl;
+    int64_t n_tiles;
     const double *kappa;
     double c, fconst;
     int nmax, smax;
@@ -240,8 +246,11 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
     using R = quad::P1Rule<D>;
     extern __shared__ __align__(16) unsigned char smem[];
     Lds<D> L(smem, a.nmax, a.smax);
-    const int64_t tile = (MODE == kColoured) ? (int64_t)a.tile_list[blockIdx.x]
-                                             : xcd_block(blockIdx.x, gridDim.x);
+    __shared__ int s_ticket;
+    int64_t tile;
+    if (MODE == kOrdered) tile = a.tile_list[take_ticket(a.ctrl, a.n_tiles, &s_ticket)];
+    else if (MODE == kColoured) tile = a.tile_list[blockIdx.x];
+    else tile = xcd_block(blockIdx.x, gridDim.x);
     const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];
     const int64_t e0 = tile * a.T;
     const int ne = (int)min((int64_t)a.T, a.E - e0);
@@ -257,7 +266,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
 #pragma unroll
         for (int i = 0; i < NP; ++i) pr[i] = a.epos[i * a.E + e];
         kap = a.kappa[e];
-        if (MODE == kColoured) sc = a.esub[e];
+        if (MODE != kAtomic) sc = a.esub[e];
     }
     const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false);
 
@@ -338,6 +347,18 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
         }
     }
     __syncthreads();
+    if (MODE == kOrdered) {
+        wait_preds(a.pred_ptr, a.pred, a.ctrl, a.n_tiles, tile);
+        ordered_rmw<8>(
+            a.values, ns, [&](int u) { const int32_t s = L.us[u]; return s < 0 ? ~s : s; },
+            [&](int u) { return L.sacc[u]; }, [&](int u) { return L.us[u] < 0; });
+        if (LOAD != FEM_LOAD_NONE)
+            ordered_rmw<4>(
+                a.rhs, nn, [&](int k) { return L.nd[k]; }, [&](int k) { return L.nacc[k]; },
+                [&](int k) { return L.nf[k] != 0; });
+        publish_done(a.ctrl, tile);
+        return;
+    }
     for (int u = threadIdx.x; u < ns; u += blockDim.x) {
         const int32_t s = L.us[u];
         const double v = L.sacc[u];
@@ -366,8 +387,11 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
     using R = quad::P1Rule<D>;
     extern __shared__ __align__(16) unsigned char smem[];
     Lds<D> L(smem, a.nmax, a.smax);
-    const int64_t tile = (MODE == kColoured) ? (int64_t)a.tile_list[blockIdx.x]
-                                             : xcd_block(blockIdx.x, gridDim.x);
+    __shared__ int s_ticket;
+    int64_t tile;
+    if (MODE == kOrdered) tile = a.tile_list[take_ticket(a.ctrl, a.n_tiles, &s_ticket)];
+    else if (MODE == kColoured) tile = a.tile_list[blockIdx.x];
+    else tile = xcd_block(blockIdx.x, gridDim.x);
     const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];
     const int64_t e0 = tile * a.T;
     const int ne = (int)min((int64_t)a.T, a.E - e0);
@@ -382,7 +406,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
 #pragma unroll
         for (int i = 0; i < NP; ++i) pr[i] = a.epos[i * a.E + e];
         kap = a.kappa[e];
-        if (MODE == kColoured) sc = a.esub[e];
+        if (MODE != kAtomic) sc = a.esub[e];
     }
     stage_tile<D>(a, L, tile, nn, false, true);
 
@@ -490,7 +514,10 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
                 xbar[0][d1] -= jb;
             }
     }
-    if (!a.gcoords) return;  // uniform: no further barriers below when coordinates are not wanted
+    if (!a.gcoords) {  // uniform: no coordinate gradient wanted
+        if (MODE == kOrdered) publish_done(a.ctrl, tile);
+        return;
+    }
     if (MODE == kAtomic) {
         if (active) {
 #pragma unroll
@@ -511,6 +538,15 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
         }
     }
     __syncthreads();
+    if (MODE == kOrdered) {
+        wait_preds(a.pred_ptr, a.pred, a.ctrl, a.n_tiles, tile);
+        ordered_rmw<4>(
+            a.gcoords, D * nn, [&](int t) { return (t / nn) * a.N + L.nd[t % nn]; },
+            [&](int t) { return L.nacc[(t / nn) * a.nmax + t % nn]; },
+            [&](int t) { return L.nf[t % nn] != 0; });
+        publish_done(a.ctrl, tile);
+        return;
+    }
     for (int k = threadIdx.x; k < nn; k += blockDim.x) {
         const int32_t n = L.nd[k];
 #pragma unroll
@@ -547,17 +583,27 @@ TileArgs base_args(const fem_pattern *p, const fem_mesh *m, const fem_form *f, c
     a.fconst = f->load_const[0];
     a.nmax = p->tile_max_nodes;
     a.smax = p->tile_max_slots;
+    a.pred_ptr = p->tpred_ptr;
+    a.pred = p->tpred;
+    a.ctrl = p->tctrl;
+    a.n_tiles = p->n_tiles;
     return a;
 }
 
 template <class K>
-void launch(K kernel, const fem_pattern *p, TileArgs a, bool coloured, size_t lds, hipStream_t s)
+void launch(K kernel, const fem_pattern *p, TileArgs a, int mode, size_t lds, hipStream_t s)
 {
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-    if (!coloured) {
+    if (mode == kAtomic) {
         a.tile_list = nullptr;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)p->n_tiles), dim3(p->tile), lds, s, a);
+        return;
+    }
+    if (mode == kOrdered) {
+        a.tile_list = p->tile_perm;
+        (void)fill_zero_i32(p->tctrl, p->n_tiles + 2, s);
         hipLaunchKernelGGL(kernel, dim3((unsigned)p->n_tiles), dim3(p->tile), lds, s, a);
         return;
     }
@@ -570,47 +616,51 @@ void launch(K kernel, const fem_pattern *p, TileArgs a, bool coloured, size_t ld
 }
 
 template <int D, int LOAD>
-int fwd_d(const fem_pattern *p, TileArgs a, bool coloured, hipStream_t s)
+int fwd_d(const fem_pattern *p, TileArgs a, int mode, hipStream_t s)
 {
     size_t lds = lds_bytes<D>(a.nmax, a.smax);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
-    if (coloured)
-        launch(k_p1_tile_fwd<D, LOAD, kColoured>, p, a, true, lds, s);
-    else
-        launch(k_p1_tile_fwd<D, LOAD, kAtomic>, p, a, false, lds, s);
+    if (mode == kOrdered) launch(k_p1_tile_fwd<D, LOAD, kOrdered>, p, a, mode, lds, s);
+    else if (mode == kColoured) launch(k_p1_tile_fwd<D, LOAD, kColoured>, p, a, mode, lds, s);
+    else launch(k_p1_tile_fwd<D, LOAD, kAtomic>, p, a, mode, lds, s);
     return FEM_OK;
 }
 
 template <int D, int LOAD>
-int bwd_d(const fem_pattern *p, TileArgs a, bool coloured, hipStream_t s)
+int bwd_d(const fem_pattern *p, TileArgs a, int mode, hipStream_t s)
 {
     size_t lds = lds_bytes<D>(a.nmax, a.smax);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
-    if (coloured)
-        launch(k_p1_tile_bwd<D, LOAD, kColoured>, p, a, true, lds, s);
-    else
-        launch(k_p1_tile_bwd<D, LOAD, kAtomic>, p, a, false, lds, s);
+    if (mode == kOrdered) launch(k_p1_tile_bwd<D, LOAD, kOrdered>, p, a, mode, lds, s);
+    else if (mode == kColoured) launch(k_p1_tile_bwd<D, LOAD, kColoured>, p, a, mode, lds, s);
+    else launch(k_p1_tile_bwd<D, LOAD, kAtomic>, p, a, mode, lds, s);
     return FEM_OK;
 }
 
 template <int D>
-int fwd_load(const fem_pattern *p, const TileArgs &a, int load, bool coloured, hipStream_t s)
+int fwd_load(const fem_pattern *p, const TileArgs &a, int load, int mode, hipStream_t s)
 {
     switch (load) {
-    case FEM_LOAD_NONE: return fwd_d<D, FEM_LOAD_NONE>(p, a, coloured, s);
-    case FEM_LOAD_CONST: return fwd_d<D, FEM_LOAD_CONST>(p, a, coloured, s);
-    default: return fwd_d<D, FEM_LOAD_SINPROD>(p, a, coloured, s);
+    case FEM_LOAD_NONE: return fwd_d<D, FEM_LOAD_NONE>(p, a, mode, s);
+    case FEM_LOAD_CONST: return fwd_d<D, FEM_LOAD_CONST>(p, a, mode, s);
+    default: return fwd_d<D, FEM_LOAD_SINPROD>(p, a, mode, s);
     }
 }
 
 template <int D>
-int bwd_load(const fem_pattern *p, const TileArgs &a, int load, bool coloured, hipStream_t s)
+int bwd_load(const fem_pattern *p, const TileArgs &a, int load, int mode, hipStream_t s)
 {
     switch (load) {
-    case FEM_LOAD_NONE: return bwd_d<D, FEM_LOAD_NONE>(p, a, coloured, s);
-    case FEM_LOAD_CONST: return bwd_d<D, FEM_LOAD_CONST>(p, a, coloured, s);
-    default: return bwd_d<D, FEM_LOAD_SINPROD>(p, a, coloured, s);
+    case FEM_LOAD_NONE: return bwd_d<D, FEM_LOAD_NONE>(p, a, mode, s);
+    case FEM_LOAD_CONST: return bwd_d<D, FEM_LOAD_CONST>(p, a, mode, s);
+    default: return bwd_d<D, FEM_LOAD_SINPROD>(p, a, mode, s);
     }
+}
+
+int scatter_mode(unsigned flags)
+{
+    if (!(flags & FEM_SCATTER_COLOURED)) return kAtomic;
+    return (flags & FEM_COLOUR_LAUNCHES) ? kColoured : kOrdered;
 }
 
 }  // namespace
@@ -619,13 +669,13 @@ int p1_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
                     double *values, double *rhs, unsigned flags, hipStream_t s)
 {
     if (p->n_tiles == 0) return FEM_OK;
-    const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
+    const int mode = scatter_mode(flags);
     TileArgs a = (m->dim == 2) ? base_args<2>(p, m, f, coef) : base_args<3>(p, m, f, coef);
     a.values = values;
     a.rhs = rhs;
-    a.use_first = coloured && !(flags & FEM_ACCUMULATE);
+    a.use_first = mode != kAtomic && !(flags & FEM_ACCUMULATE);
     const int load = rhs ? f->load : FEM_LOAD_NONE;
-    int rc = (m->dim == 2) ? fwd_load<2>(p, a, load, coloured, s) : fwd_load<3>(p, a, load, coloured, s);
+    int rc = (m->dim == 2) ? fwd_load<2>(p, a, load, mode, s) : fwd_load<3>(p, a, load, mode, s);
     if (rc != FEM_OK) return rc;
     FEM_HIP_TRY(hipGetLastError());
     return FEM_OK;
@@ -636,16 +686,16 @@ int p1_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
                      double *gcoef, double *gcoords, unsigned flags, hipStream_t s)
 {
     if (p->n_tiles == 0) return FEM_OK;
-    const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
+    const int mode = scatter_mode(flags);
     TileArgs a = (m->dim == 2) ? base_args<2>(p, m, f, coef) : base_args<3>(p, m, f, coef);
     a.gvalues = gvalues;
     a.grhs = grhs;
     a.gkappa = gcoef;
     a.gcoords = gcoords;
     a.accumulate = (flags & FEM_ACCUMULATE) != 0;
-    a.use_first = coloured && !a.accumulate;
+    a.use_first = mode != kAtomic && !a.accumulate;
     const int load = grhs ? f->load : FEM_LOAD_NONE;
-    int rc = (m->dim == 2) ? bwd_load<2>(p, a, load, coloured, s) : bwd_load<3>(p, a, load, coloured, s);
+    int rc = (m->dim == 2) ? bwd_load<2>(p, a, load, mode, s) : bwd_load<3>(p, a, load, mode, s);
     if (rc != FEM_OK) return rc;
     FEM_HIP_TRY(hipGetLastError());
     return FEM_OK;

@@ -25,7 +25,7 @@ namespace fem {
 
 namespace {
 
-enum Mode : int { kAtomic = 0, kColoured = 1 };
+enum Mode : int { kAtomic = 0, kColoured = 1, kOrdered = 2 };
 constexpr int kP2Threads = 256;  // four wavefronts
 constexpr int NPE = 10;
 
@@ -84,9 +84,12 @@ struct P2Args {
     const uint64_t *trun;    // 2 words per tile node
     const uint64_t *tfirst;  // 2 words per tile node
     const uint8_t *trfirst;
-    const uint16_t *enode;  // [10][E]
-    const uint8_t *epos;    // [100][E]
+    const uint16_t *enode;  // [E][10] tile-node index of each local node
+    const uint8_t *epos;    // [E][100] row position of each local pair
     const int32_t *tile_list;
+    const int32_t *pred_ptr, *pred;
+    int32_t *ctrl;
+    int64_t n_tiles;
     const double *lam, *mu;
     int load;
     double bf[3];
@@ -98,7 +101,7 @@ struct P2Args {
 // LDS carve-up
 struct P2Lds {
     double *R;      // [14][10][3] reference gradients
-    double *G;      // [32][32] Gram matrix of the current element
+    double *G;      // [4][32][32] Gram matrices of the wavefronts' current elements
     double *acc;    // [smax][9] pair accumulators
     double *xs;     // [3][nmax]
     double *racc;   // [3][nmax]
@@ -115,7 +118,7 @@ struct P2Lds {
     {
         R = (double *)b;
         G = R + 14 * 10 * 3;
-        acc = G + 32 * 32;
+        acc = G + 4 * 32 * 32;
         xs = acc + 9 * smax;
         racc = xs + 3 * nmax;
         rb = (uint64_t *)(racc + 3 * nmax);
@@ -132,7 +135,7 @@ struct P2Lds {
 
 size_t p2_lds_bytes(int nmax, int smax, int T)
 {
-    return sizeof(double) * (size_t)(420 + 1024 + 9 * smax + 6 * nmax) + sizeof(uint64_t) * 2 * nmax +
+    return sizeof(double) * (size_t)(420 + 4 * 1024 + 9 * smax + 6 * nmax) + sizeof(uint64_t) * 2 * nmax +
            sizeof(int32_t) * (size_t)(4 * nmax + smax + 16) + sizeof(uint16_t) * 100 * T + nmax + 16;
 }
 
@@ -190,15 +193,14 @@ __device__ __forceinline__ void p2_geometry(const double x[4][3], double inv[3][
     vol = fabs(det) * (1.0 / 6.0);
 }
 
-// sqrt(w_q |T|) d_a phi_i (x_q) for column c = 3i + a (0 beyond 30 columns / 14 points)
-__device__ __forceinline__ double pval(const double *R, int q, int c, const double inv[3][3],
-                                       double vol)
+// sqrt(w_q) d_a phi_i (x_q) for column c = 3i + a (0 beyond 30 columns / 14 points); the
+// table R holds sqrt(w_q) times the reference gradients
+__device__ __forceinline__ double pval(const double *R, int q, int c, const double inv[3][3])
 {
     if (q >= 14 || c >= 30) return 0.0;
     const int i = c / 3, a = c - 3 * (c / 3);
     const double *r = R + (q * 10 + i) * 3;
-    const double g = r[0] * inv[0][a] + r[1] * inv[1][a] + r[2] * inv[2][a];
-    return sqrt(quad::Tet14::w(q) * vol) * g;
+    return r[0] * inv[0][a] + r[1] * inv[1][a] + r[2] * inv[2][a];
 }
 
 template <int MODE, bool F32>
@@ -206,18 +208,21 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     P2Lds L(smem, a.nmax, a.smax, a.T);
+    __shared__ int s_ticket;
     const int tid = threadIdx.x;
-    const int64_t tile = (MODE == kColoured) ? (int64_t)a.tile_list[blockIdx.x]
-                                             : xcd_block(blockIdx.x, gridDim.x);
+    int64_t tile;
+    if (MODE == kOrdered) tile = a.tile_list[take_ticket(a.ctrl, a.n_tiles, &s_ticket)];
+    else if (MODE == kColoured) tile = a.tile_list[blockIdx.x];
+    else tile = xcd_block(blockIdx.x, gridDim.x);
     const int n0 = a.tnode_ptr[tile];
     const int nn = a.tnode_ptr[tile + 1] - n0;
     const int64_t e0 = tile * a.T;
     const int ne = (int)min((int64_t)a.T, a.E - e0);
 
-    // ---- stage: reference gradients, tile nodes, distinct pairs ----
+    // ---- stage: reference gradients (scaled by sqrt(w_q)), tile nodes, distinct pairs ----
     for (int t = tid; t < 14 * 10 * 3; t += kP2Threads) {
         const int q = t / 30, i = (t / 3) % 10, m = t % 3;
-        L.R[t] = ref_grad(q, i, m);
+        L.R[t] = sqrt(quad::Tet14::w(q)) * ref_grad(q, i, m);
     }
     const int per = (nn + kP2Threads - 1) / kP2Threads;
     const int k0 = min(nn, tid * per), k1 = min(nn, k0 + per);
@@ -255,88 +260,169 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
         }
     }
     __syncthreads();
-    // pair index of every (element, i, j) of the tile
     for (int t = tid; t < ne * 100; t += kP2Threads) {
         const int el = t / 100, ij = t - 100 * el, i = ij / 10;
         const int64_t e = e0 + el;
-        const int ki = a.enode[(int64_t)i * a.E + e];
-        const int p = a.epos[(int64_t)ij * a.E + e];
+        const int ki = a.enode[e * NPE + i];
+        const int p = a.epos[e * NPE * NPE + ij];
         L.lp[el * 100 + ij] = (uint16_t)(L.ust[ki] + popc_below(&L.rb[2 * ki], p));
     }
     __syncthreads();
 
-    // ---- elements, one at a time ----
+    // ---- elements: one per wavefront, four in flight ----
     const int wave = tid >> 6, lane = tid & 63;
-    const int rblk = wave >> 1, cblk = wave & 1;
-    for (int el = 0; el < ne; ++el) {
-        const int64_t e = e0 + el;
-        double x[4][3];
+    double *G = L.G + wave * 32 * 32;
+    for (int base = 0; base < ne; base += 4) {
+        const int el = base + wave;
+        const bool has = el < ne;
+        double lm = 0.0, mm = 0.0, vol = 0.0;
+        if (has) {
+            const int64_t e = e0 + el;
+            double x[4][3];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int kv = a.enode[(int64_t)v * a.E + e];
+            for (int v = 0; v < 4; ++v) {
+                const int kv = a.enode[e * NPE + v];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) x[v][d] = L.xs[d * a.nmax + kv];
-        }
-        double inv[3][3], vol;
-        p2_geometry(x, inv, vol);
-        // one 16x16 tile of G per wavefront: rows rblk*16.., columns cblk*16..
-        const int rc = rblk * 16 + (lane & 15), cc = cblk * 16 + (lane & 15);
-        if constexpr (F32) {
-            f4_t g = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int q = 4 * ks + (lane >> 4);
-                const float av = (float)pval(L.R, q, rc, inv, vol);
-                const float bv = (float)pval(L.R, q, cc, inv, vol);
-                g = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, g, 0, 0, 0);
+                for (int d = 0; d < 3; ++d) x[v][d] = L.xs[d * a.nmax + kv];
             }
-            // f32 16x16x4 output layout: register r of lane l holds row 4 (l / 16) + r
+            double inv[3][3];
+            p2_geometry(x, inv, vol);
+            const double sv = sqrt(vol);
+            lm = a.lam[e];
+            mm = a.mu[e];
+            // G = P^T P, symmetric: output tiles (0,0), (0,1), (1,1); (1,0) by transposition
+            const int lo = lane & 15, hi = lane >> 4;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                L.G[(rblk * 16 + 4 * (lane >> 4) + r) * 32 + cblk * 16 + (lane & 15)] = (double)g[r];
-        } else {
-            d4_t g = {0.0, 0.0, 0.0, 0.0};
+            for (int tb = 0; tb < 3; ++tb) {
+                const int rb = tb == 2 ? 1 : 0, cb = tb == 0 ? 0 : 1;
+                const int rc = rb * 16 + lo, cc = cb * 16 + lo;
+                if constexpr (F32) {
+                    f4_t g = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int q = 4 * ks + (lane >> 4);
-                const double av = pval(L.R, q, rc, inv, vol);
-                const double bv = pval(L.R, q, cc, inv, vol);
-                g = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, g, 0, 0, 0);
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int q = 4 * ks + hi;
+                        const float av = (float)(sv * pval(L.R, q, rc, inv));
+                        const float bv = (float)(sv * pval(L.R, q, cc, inv));
+                        g = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, g, 0, 0, 0);
+                    }
+                    // f32 16x16x4 output layout: register r of lane l holds row 4 (l / 16) + r
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int R = rb * 16 + 4 * hi + r, C = cb * 16 + lo;
+                        G[R * 32 + C] = (double)g[r];
+                        if (tb == 1) G[C * 32 + R] = (double)g[r];
+                    }
+                } else {
+                    d4_t g = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int q = 4 * ks + hi;
+                        const double av = sv * pval(L.R, q, rc, inv);
+                        const double bv = sv * pval(L.R, q, cc, inv);
+                        g = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, g, 0, 0, 0);
+                    }
+                    // f64 16x16x4 output layout (measured on gfx950): register r of lane l
+                    // holds row (l / 16) + 4 r, column l % 16
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int R = rb * 16 + hi + 4 * r, C = cb * 16 + lo;
+                        G[R * 32 + C] = g[r];
+                        if (tb == 1) G[C * 32 + R] = g[r];
+                    }
+                }
             }
-            // f64 16x16x4 output layout (measured on gfx950): register r of lane l holds
-            // row (l / 16) + 4 r, column l % 16
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                L.G[(rblk * 16 + (lane >> 4) + 4 * r) * 32 + cblk * 16 + (lane & 15)] = g[r];
         }
-        __syncthreads();
-        if (tid < 100) {
-            // node pair (i, j): K block from the 3x3 block of G and its transpose
-            const int i = tid / 10, j = tid - 10 * (tid / 10);
-            const double lm = a.lam[e], mm = a.mu[e];
-            double gb[3][3];
+        // the Gram matrix was written by other lanes of this wavefront
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // K blocks of this wavefront's element: lanes take node pairs (i, j)
+        double kb[2][9];
+        int lpi[2] = {0, 0};
 #pragma unroll
-            for (int p = 0; p < 3; ++p)
+        for (int h = 0; h < 2; ++h) {
+            const int pr = lane + 64 * h;
+            if (has && pr < 100) {
+                const int i = pr / 10, j = pr - 10 * (pr / 10);
+                double gb[3][3];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) gb[p][q] = L.G[(3 * i + p) * 32 + 3 * j + q];
-            const double tr = gb[0][0] + gb[1][1] + gb[2][2];
-            double *dst = L.acc + 9 * (int)L.lp[el * 100 + tid];
+                for (int p = 0; p < 3; ++p)
 #pragma unroll
-            for (int p = 0; p < 3; ++p)
+                    for (int q = 0; q < 3; ++q) gb[p][q] = G[(3 * i + p) * 32 + 3 * j + q];
+                const double tr = gb[0][0] + gb[1][1] + gb[2][2];
 #pragma unroll
-                for (int q = 0; q < 3; ++q)
-                    dst[3 * p + q] += lm * gb[p][q] + mm * gb[q][p] + (p == q ? mm * tr : 0.0);
-        } else if (a.load == FEM_LOAD_CONST && tid >= 128 && tid < 158) {
+                for (int p = 0; p < 3; ++p)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        kb[h][3 * p + q] = lm * gb[p][q] + mm * gb[q][p] + (p == q ? mm * tr : 0.0);
+                lpi[h] = L.lp[el * 100 + pr];
+            }
+        }
+        // all reads of G done before the next element overwrites it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double bfv[3] = {0.0, 0.0, 0.0};
+        int bnode = 0;
+        if (a.load == FEM_LOAD_CONST && has && lane < 10) {
             // body force: b[(i,c)] = f_c |T| (1/|T|) int phi_i
-            const int t = tid - 128, i = t / 3, c = t - 3 * (t / 3);
-            const int ki = a.enode[(int64_t)i * a.E + e];
-            L.racc[c * a.nmax + ki] += a.bf[c] * vol * phi_mean(i);
+            bnode = a.enode[(e0 + el) * NPE + lane];
+            const double pm = phi_mean(lane);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bfv[c] = a.bf[c] * vol * pm;
         }
-        __syncthreads();
+        if (MODE == kAtomic) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (has && lane + 64 * h < 100)
+#pragma unroll
+                    for (int v = 0; v < 9; ++v) atomicAdd(&L.acc[9 * lpi[h] + v], kb[h][v]);
+            if (a.load == FEM_LOAD_CONST && has && lane < 10)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) atomicAdd(&L.racc[c * a.nmax + bnode], bfv[c]);
+        } else {
+            // deterministic: the four elements are added in element order
+            for (int w2 = 0; w2 < 4; ++w2) {
+                if (wave == w2) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        if (has && lane + 64 * h < 100)
+#pragma unroll
+                            for (int v = 0; v < 9; ++v) L.acc[9 * lpi[h] + v] += kb[h][v];
+                    if (a.load == FEM_LOAD_CONST && has && lane < 10)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) L.racc[c * a.nmax + bnode] += bfv[c];
+                }
+                __syncthreads();
+            }
+        }
     }
+    __syncthreads();
 
     // ---- one global update per distinct (pair, a, b) and per (node, a) ----
     const int nvals = 9 * total;
+    if (MODE == kOrdered) {
+        wait_preds(a.pred_ptr, a.pred, a.ctrl, a.n_tiles, tile);
+        auto slot_of = [&](int t) {
+            const int ra = t / (3 * total), rest = t - ra * 3 * total;
+            const int u = rest / 3, cb = rest - 3 * (rest / 3);
+            const int32_t code = L.us[u];
+            const int k = (code >> 8) & 0xffff, p = code & 0xff;
+            return 9 * (int64_t)L.rp[k] + 3 * (int64_t)ra * L.rl[k] + 3 * p + cb;
+        };
+        auto val_of = [&](int t) {
+            const int ra = t / (3 * total), rest = t - ra * 3 * total;
+            const int u = rest / 3, cb = rest - 3 * (rest / 3);
+            return L.acc[9 * u + 3 * ra + cb];
+        };
+        auto first_of = [&](int t) { return L.us[(t - (t / (3 * total)) * 3 * total) / 3] < 0; };
+        ordered_rmw<8>(a.values, nvals, slot_of, val_of, first_of);
+        if (a.load == FEM_LOAD_CONST)
+            ordered_rmw<4>(
+                a.rhs, 3 * nn, [&](int t) { return 3 * (int64_t)L.nd[t / 3] + t % 3; },
+                [&](int t) { return L.racc[(t % 3) * a.nmax + t / 3]; },
+                [&](int t) { return L.nf[t / 3] != 0; });
+        publish_done(a.ctrl, tile);
+        return;
+    }
     for (int t = tid; t < nvals; t += kP2Threads) {
         const int ra = t / (3 * total), rest = t - ra * 3 * total;
         const int u = rest / 3, cb = rest - 3 * (rest / 3);
@@ -361,13 +447,19 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
 }
 
 template <class K>
-void p2_launch(K kernel, const fem_pattern *p, P2Args a, bool coloured, size_t lds, hipStream_t s)
+void p2_launch(K kernel, const fem_pattern *p, P2Args a, int mode, size_t lds, hipStream_t s)
 {
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-    if (!coloured) {
+    if (mode == kAtomic) {
         a.tile_list = nullptr;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)p->n_tiles), dim3(kP2Threads), lds, s, a);
+        return;
+    }
+    if (mode == kOrdered) {
+        a.tile_list = p->tile_perm;
+        (void)fill_zero_i32(p->tctrl, p->n_tiles + 2, s);
         hipLaunchKernelGGL(kernel, dim3((unsigned)p->n_tiles), dim3(kP2Threads), lds, s, a);
         return;
     }
@@ -385,7 +477,8 @@ int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
                     double *values, double *rhs, unsigned flags, hipStream_t s)
 {
     if (p->n_tiles == 0) return FEM_OK;
-    const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
+    const int mode = !(flags & FEM_SCATTER_COLOURED) ? kAtomic
+                     : ((flags & FEM_COLOUR_LAUNCHES) ? kColoured : kOrdered);
     P2Args a{};
     a.coords = m->coords;
     a.N = m->n_nodes;
@@ -399,6 +492,10 @@ int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
     a.trfirst = p->trfirst;
     a.enode = p->enode16;
     a.epos = p->epos8;
+    a.pred_ptr = p->tpred_ptr;
+    a.pred = p->tpred;
+    a.ctrl = p->tctrl;
+    a.n_tiles = p->n_tiles;
     a.lam = coef;
     a.mu = coef + m->n_elems;
     a.load = rhs ? f->load : FEM_LOAD_NONE;
@@ -407,17 +504,20 @@ int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
     a.rhs = rhs;
     a.nmax = p->tile_max_nodes;
     a.smax = p->tile_max_slots;
-    a.use_first = coloured && !(flags & FEM_ACCUMULATE);
+    a.use_first = mode != kAtomic && !(flags & FEM_ACCUMULATE);
     if (a.T > 64) return fail(FEM_ERR_UNSUPPORTED, "P2 tiles hold at most 64 elements");
     const size_t lds = p2_lds_bytes(a.nmax, a.smax, a.T);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "P2 tile needs more LDS than a CU has");
     const bool f32 = (flags & FEM_PREC_FP32) != 0;
-    if (coloured) {
-        if (f32) p2_launch(k_p2_tile_fwd<kColoured, true>, p, a, true, lds, s);
-        else p2_launch(k_p2_tile_fwd<kColoured, false>, p, a, true, lds, s);
+    if (mode == kOrdered) {
+        if (f32) p2_launch(k_p2_tile_fwd<kOrdered, true>, p, a, mode, lds, s);
+        else p2_launch(k_p2_tile_fwd<kOrdered, false>, p, a, mode, lds, s);
+    } else if (mode == kColoured) {
+        if (f32) p2_launch(k_p2_tile_fwd<kColoured, true>, p, a, mode, lds, s);
+        else p2_launch(k_p2_tile_fwd<kColoured, false>, p, a, mode, lds, s);
     } else {
-        if (f32) p2_launch(k_p2_tile_fwd<kAtomic, true>, p, a, false, lds, s);
-        else p2_launch(k_p2_tile_fwd<kAtomic, false>, p, a, false, lds, s);
+        if (f32) p2_launch(k_p2_tile_fwd<kAtomic, true>, p, a, mode, lds, s);
+        else p2_launch(k_p2_tile_fwd<kAtomic, false>, p, a, mode, lds, s);
     }
     FEM_HIP_TRY(hipGetLastError());
     return FEM_OK;

@@ -104,7 +104,9 @@ __device__ __forceinline__ uint32_t prio_hash(uint32_t x)
 // also write the per-element node indices and row positions and the per-node masks of
 // row positions (MW 64-bit words per node).  PACKED (P1): node indices as four 16-bit
 // fields of one uint64 per element, positions as four bytes of one uint32 per element
-// row.  Otherwise (P2): node indices uint16 [npe][E], positions uint8 [npe*npe][E].
+// row.  Otherwise (P2): element-major node indices uint16 [E][npe] and positions uint8
+// [E][npe*npe] (a P2 tile reads every entry of its elements, so element-major is the
+// coalesced layout).
 template <bool FILL, int MW, bool PACKED>
 __global__ __launch_bounds__(kTT) void k_tile_nodes(const int32_t *__restrict__ conn, int64_t E,
                                                     int npe, int T, int32_t *__restrict__ tile_nn,
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(kTT) void k_tile_nodes(const int32_t *__restrict__ 
         int32_t node = conn[(int64_t)k * E + e];
         uint16_t li = (uint16_t)lower_bound_i32(un, total, node);
         if (PACKED) reinterpret_cast<uint16_t *>((uint64_t *)enode_v + e)[k] = li;
-        else ((uint16_t *)enode_v)[(int64_t)k * E + e] = li;
+        else ((uint16_t *)enode_v)[e * npe + k] = li;
     }
     for (int idx = threadIdx.x; idx < cnt * npe; idx += kTT) {
         int ij = idx / ne, el = idx - ij * ne;
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(kTT) void k_tile_nodes(const int32_t *__restrict__ 
             p = 0;
         }
         if (PACKED) reinterpret_cast<uint8_t *>((uint32_t *)epos_v + (int64_t)i * E + e)[j] = (uint8_t)p;
-        else ((uint8_t *)epos_v)[(int64_t)ij * E + e] = (uint8_t)p;
+        else ((uint8_t *)epos_v)[e * npe * npe + ij] = (uint8_t)p;
         int li = lower_bound_i32(un, total, row);
         atomicOr(&rb[li * MW + (p >> 6)], 1ull << (p & 63));
     }
@@ -318,6 +320,57 @@ __global__ __launch_bounds__(kTT) void k_tile_first(const int32_t *__restrict__ 
     }
 }
 
+// Lower-colour neighbour tiles of every tile (tiles sharing a node), ascending, distinct.
+template <bool FILL>
+__global__ __launch_bounds__(kTT) void k_tile_preds(const int32_t *__restrict__ tcol,
+                                                    const int32_t *__restrict__ tnode_ptr,
+                                                    const int32_t *__restrict__ tnode,
+                                                    const int32_t *__restrict__ n2t_ptr,
+                                                    const int32_t *__restrict__ n2t,
+                                                    int32_t *__restrict__ cnt,
+                                                    const int32_t *__restrict__ ptr,
+                                                    int32_t *__restrict__ pred, int *err)
+{
+    constexpr int kCap = 4096;
+    __shared__ int32_t sh[kCap];
+    __shared__ int ncand;
+    __shared__ int scan_sh[kTT];
+    const int32_t t = blockIdx.x;
+    const int32_t c = tcol[t];
+    if (threadIdx.x == 0) ncand = 0;
+    __syncthreads();
+    for (int32_t k = tnode_ptr[t] + threadIdx.x; k < tnode_ptr[t + 1]; k += kTT) {
+        const int32_t n = tnode[k];
+        for (int32_t j = n2t_ptr[n]; j < n2t_ptr[n + 1]; ++j) {
+            const int32_t t2 = n2t[j];
+            if (t2 != t && tcol[t2] < c) {
+                int slot = atomicAdd(&ncand, 1);
+                if (slot < kCap) sh[slot] = t2;
+                else atomicOr(err, kErrTilesPerNode);
+            }
+        }
+    }
+    __syncthreads();
+    const int cntc = min(ncand, kCap);
+    const int P = next_pow2(cntc);
+    for (int i = cntc + threadIdx.x; i < P; i += kTT) sh[i] = INT32_MAX;
+    __syncthreads();
+    block_bitonic<kTT>(sh, P);
+    const int per = (P + kTT - 1) / kTT;
+    const int b0 = min(P, (int)threadIdx.x * per), b1 = min(P, b0 + per);
+    int local = 0;
+    for (int i = b0; i < b1; ++i)
+        local += (sh[i] != INT32_MAX && (i == 0 || sh[i] != sh[i - 1])) ? 1 : 0;
+    int total;
+    int off = block_scan_excl<kTT>(local, scan_sh, &total);
+    if (!FILL) {
+        if (threadIdx.x == 0) cnt[t] = total;
+        return;
+    }
+    for (int i = b0; i < b1; ++i)
+        if (sh[i] != INT32_MAX && (i == 0 || sh[i] != sh[i - 1])) pred[ptr[t] + off++] = sh[i];
+}
+
 // Greedy colouring of the elements inside each tile, in element order.
 template <bool PACKED>
 __global__ __launch_bounds__(kTT) void k_tile_subcolour(const void *__restrict__ enode_v, int npe,
@@ -337,7 +390,7 @@ __global__ __launch_bounds__(kTT) void k_tile_subcolour(const void *__restrict__
     for (int idx = threadIdx.x; idx < ne * npe; idx += kTT) {
         int k = idx / ne, el = idx - k * ne;
         en[el * npe + k] = PACKED ? (uint16_t)(((const uint64_t *)enode_v)[e0 + el] >> (16 * k))
-                                  : ((const uint16_t *)enode_v)[(int64_t)k * E + e0 + el];
+                                  : ((const uint16_t *)enode_v)[(e0 + el) * npe + k];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -527,10 +580,23 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
         hipLaunchKernelGGL(k_tile_subcolour<false>, dim3((unsigned)nt), dim3(kTT), 0, s,
                            (const void *)p->enode16, npe, E, T, p->tnode_ptr, p->esub, p->tile_nsub,
                            d_err);
+    // predecessors for the ordered single-launch coloured scatter
+    int32_t *pcnt = nullptr;
+    FEM_TRY(tmp.get(&pcnt, nt));
+    hipLaunchKernelGGL(k_tile_preds<false>, dim3((unsigned)nt), dim3(kTT), 0, s, p->tile_colour,
+                       p->tnode_ptr, p->tnode, n2t_ptr, n2t, pcnt, nullptr, nullptr, d_err);
+    FEM_TRY(pattern_alloc(p, (void **)&p->tpred_ptr, sizeof(int32_t) * (nt + 1)));
+    int64_t n_pred = 0;
+    FEM_TRY(scan_to_i32(tmp, pcnt, nt, p->tpred_ptr, &n_pred, s));
+    FEM_TRY(pattern_alloc(p, (void **)&p->tpred, sizeof(int32_t) * n_pred));
+    hipLaunchKernelGGL(k_tile_preds<true>, dim3((unsigned)nt), dim3(kTT), 0, s, p->tile_colour,
+                       p->tnode_ptr, p->tnode, n2t_ptr, n2t, nullptr, p->tpred_ptr, p->tpred, d_err);
+    FEM_TRY(pattern_alloc(p, (void **)&p->tctrl, sizeof(int32_t) * (nt + 2)));
     FEM_HIP_TRY(hipGetLastError());
     FEM_HIP_TRY(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
     FEM_HIP_TRY(hipStreamSynchronize(s));
     if (h_err & kErrMissing) return fail(FEM_ERR_HIP, "internal: tile node lookup failed");
+    if (h_err & kErrTilesPerNode) return fail(FEM_ERR_UNSUPPORTED, "tile plan: too many neighbour tiles");
     if (h_err & kErrSub) return fail(FEM_ERR_UNSUPPORTED, "tile plan: more than 64 colours in a tile");
     p->has_tiles = true;
     return FEM_OK;

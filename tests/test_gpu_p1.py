@@ -228,6 +228,25 @@ def test_coloured_is_bitwise_reproducible():
     assert all(o == outs[0] for o in outs)
 
 
+@pytest.mark.parametrize("name", ["tri32", "tet12"])
+def test_ordered_single_launch_equals_colour_launches(name):
+    """The single-launch coloured scatter applies every slot's contributions in the same
+    colour order as one launch per colour: bitwise identical outputs and adjoint."""
+    m = MESHES[name]()
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kap = torch.from_numpy(meshgen.coefficients(m.n_elems, "helmholtz", seed=13)).cuda()
+    G, g = (torch.from_numpy(a).cuda() for a in meshgen.upstream_grads(pat.nnz, pat.n_rows, seed=13))
+    form = F.Form("helmholtz", "sinprod")
+    outs = {}
+    for sc in ("coloured", "coloured-launches"):
+        v, r = F.assemble(pat, d, form, kap, scatter=sc)
+        gk, gx = F.assemble_backward(pat, d, form, kap, G, g, scatter=sc)
+        outs[sc] = [_np(t).tobytes() for t in (v, r, gk, gx)]
+    assert outs["coloured"] == outs["coloured-launches"]
+
+
 @pytest.mark.parametrize("scatter", ["atomic", "coloured"])
 def test_accumulate_adds(scatter):
     """FEM_ACCUMULATE adds the assembled system onto what the buffers hold."""
