@@ -147,26 +147,31 @@ def cube_tet(n: int, order: int = 1, jitter: float = 0.2, seed: int = 0) -> Mesh
         coords = _jitter(grid, n, jitter, seed)
         return Mesh(3, 1, n, np.ascontiguousarray(coords), np.ascontiguousarray(vid.astype(np.int32)))
 
-    # P2 on the half grid
+    # P2 on the half grid: node id x + m (y + m z) for half-grid position (x, y, z); the
+    # id is linear in the position, so an edge node's id is the mean of its end vertices'
     m = 2 * n + 1
-    hp = 2 * vpos  # half-grid positions of vertices [4][3][E]
-    E = hp.shape[2]
-    allpos = np.empty((10, 3, E), dtype=np.int64)
-    allpos[:4] = hp
+    E = vpos.shape[2]
+    hid = np.empty((10, E), dtype=np.int64)
+    hid[:4] = 2 * (vpos[:, 0, :] + m * (vpos[:, 1, :] + m * vpos[:, 2, :]))
     for k, (a, b) in enumerate(P2_EDGES):
-        allpos[4 + k] = (hp[a] + hp[b]) // 2
-    hid = allpos[:, 0, :] + m * (allpos[:, 1, :] + m * allpos[:, 2, :])
-    # vertex coordinates: jitter on the vertex lattice, then place on the half grid
+        hid[4 + k] = (hid[a] + hid[b]) // 2
+    # vertex coordinates: jitter on the vertex lattice
     mv = n + 1
     kk, jj, ii = np.meshgrid(np.arange(mv), np.arange(mv), np.arange(mv), indexing="ij")
     vgrid = np.stack([ii.ravel(), jj.ravel(), kk.ravel()])
     vx = _jitter(vgrid, n, jitter, seed)
-    coords = np.full((3, m ** 3), np.nan)
-    vh = 2 * vgrid
-    coords[:, vh[0] + m * (vh[1] + m * vh[2])] = vx
-    for k, (a, b) in enumerate(P2_EDGES):
-        coords[:, hid[4 + k]] = 0.5 * (coords[:, hid[a]] + coords[:, hid[b]])
-    assert not np.isnan(coords).any(), "half-grid node not covered by any element"
+    # every half-grid node is a vertex (all coordinates even) or the midpoint of the
+    # edge between pos - s and pos + s, s = its odd coordinates: all Kuhn edges run along
+    # 0/1 directions
+    hz, hy, hx = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    pos = np.stack([hx.ravel(), hy.ravel(), hz.ravel()])
+    odd = pos & 1
+    lo = (pos - odd) // 2
+    hi = (pos + odd) // 2
+    vlo = lo[0] + mv * (lo[1] + mv * lo[2])
+    vhi = hi[0] + mv * (hi[1] + mv * hi[2])
+    is_vertex = ~odd.any(axis=0)
+    coords = np.where(is_vertex[None, :], vx[:, vlo], 0.5 * (vx[:, vlo] + vx[:, vhi]))
     return Mesh(3, 2, n, np.ascontiguousarray(coords), np.ascontiguousarray(hid.astype(np.int32)))
 
 
