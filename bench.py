@@ -8,7 +8,10 @@ values and RHS plus the assembly kernel (geometry, quadrature, scatter-add), inp
 already resident in HBM.  The pattern (built once per mesh) is timed separately.
 
 Prints one JSON line.  Extra fields: the coloured scatter, the adjoint (dL/dkappa and
-dL/dx) and its ratio to the forward, the matrix-only forward, the pattern build.
+dL/dx) and its ratio to the forward, the matrix-only forward, the pattern build; P2
+elasticity on the 40^3 cube (forward FP64 / FP32 matrix cores, adjoint); the mixed batch
+of 512 meshes (one launch per element family against 512 per-mesh calls, plain and
+graph-captured).
 """
 
 from __future__ import annotations
@@ -88,7 +91,119 @@ def _bench_p2(torch, fem, meshgen, dev, steps):
                      "alg_GBps": alg / (ms * 1e-3) / 1e9,
                      "mfma_util": E * mfma_flops / (ms * 1e-3) / (157.3e12 if "f32" in name else 78.6e12),
                      "useful_tflops": E * useful_flops / (ms * 1e-3) / 1e12}
+    # adjoint: dL/dlambda, dL/dmu, dL/dx; per element 2 x 16 v_mfma_f64_16x16x4f64
+    G = torch.randn(pat.nnz, dtype=torch.float64, device=dev,
+                    generator=torch.Generator(device=dev).manual_seed(1))
+    g = torch.randn(pat.n_rows, dtype=torch.float64, device=dev,
+                    generator=torch.Generator(device=dev).manual_seed(2))
+    gc = torch.empty_like(coef)
+    gx = torch.empty_like(dm.coords)
+    for name, sc in (("bwd_atomic", "atomic"), ("bwd_coloured", "coloured")):
+        def bstep():
+            fem.assemble_backward(pat, dm, form, coef, G, g, grad_coef=gc, grad_coords=gx, scatter=sc)
+        bstep()
+        ms = _time_calls(torch, bstep, steps)
+        out[name] = {"ms": ms, "elements_per_s": E / (ms * 1e-3),
+                     "mfma_util": E * 2 * mfma_flops / (ms * 1e-3) / 78.6e12,
+                     "bwd_over_fwd": ms / out["atomic_f64" if sc == "atomic" else "coloured_f64"]["ms"]}
+    del G, g
     pat.close()
+    return out
+
+
+def _bench_batch(torch, fem, meshgen, dev, steps):
+    """512 meshes, n ~ U{6..32}, 6 n^3 tets each, half P1 Helmholtz (kappa, sin load),
+    half P2 elasticity (lambda, mu, body force): one block-diagonal system."""
+    plan = meshgen.batch_plan(512, 6, 32, seed=0)
+    t0 = time.perf_counter()
+    meshes, forms, coefs = [], [], []
+    for n, order, kind, seed in plan:
+        m = meshgen.cube_tet(n, order, seed=seed)
+        meshes.append(fem.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev), order))
+        forms.append(fem.Form("elasticity", "const", load_const=(0.0, 0.0, -1.0)) if kind == "elasticity"
+                     else fem.Form("helmholtz", "sinprod", reaction=1.0))
+        coefs.append(torch.from_numpy(meshgen.coefficients(m.n_elems, kind, seed=seed)).to(dev))
+    gen_s = time.perf_counter() - t0
+    E = sum(m.n_elems for m in meshes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = fem.Batch(meshes)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    pats = [fem.Pattern(m, ncomp=3 if m.order == 2 else 1) for m in meshes]
+    values = torch.empty(b.nnz, dtype=torch.float64, device=dev)
+    rhs = torch.empty(b.n_rows, dtype=torch.float64, device=dev)
+    vblk = [b.block(values, k) for k in range(len(meshes))]
+    rblk = [b.block(rhs, k, rows=True) for k in range(len(meshes))]
+    out = {"workload": "512 meshes, n ~ U{6..32}, 6n^3 tets each, half P1 Helmholtz (sin load), "
+                       "half P2 elasticity (body force); block-diagonal CSR, int64 offsets",
+           "n_meshes": len(meshes), "n_elems": E, "n_rows": b.n_rows, "nnz": b.nnz,
+           "n_tiles": b.n_tiles, "host_generation_s": gen_s, "batch_build_ms": build_ms}
+
+    def batched(sc):
+        return lambda: fem.assemble_batch(b, meshes, forms, coefs, values, rhs, scatter=sc)
+
+    def per_mesh(sc):
+        def f():
+            for k in range(len(meshes)):
+                fem.assemble(pats[k], meshes[k], forms[k], coefs[k], vblk[k], rblk[k], scatter=sc)
+        return f
+
+    def graphed(fn):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            fn()
+        return gr.replay
+
+    reps = max(2, steps // 10)
+    for sc in ("coloured", "atomic"):
+        res = {}
+        for name, fn in (("batched", batched(sc)), ("per_mesh_loop", per_mesh(sc))):
+            fn()
+            res[name + "_ms"] = _time_calls(torch, fn, reps)
+            res[name + "_graph_ms"] = _time_calls(torch, graphed(fn), reps)
+        res["elements_per_s"] = E / (res["batched_graph_ms"] * 1e-3)
+        res["speedup_vs_per_mesh_loop"] = res["per_mesh_loop_ms"] / res["batched_graph_ms"]
+        res["speedup_vs_per_mesh_graph"] = res["per_mesh_loop_graph_ms"] / res["batched_graph_ms"]
+        out["fwd_" + sc] = res
+    # forward + adjoint (coloured)
+    G = torch.randn(b.nnz, dtype=torch.float64, device=dev,
+                    generator=torch.Generator(device=dev).manual_seed(3))
+    g = torch.randn(b.n_rows, dtype=torch.float64, device=dev,
+                    generator=torch.Generator(device=dev).manual_seed(4))
+    gcs = [torch.empty_like(c) for c in coefs]
+    gxs = [torch.empty_like(m.coords) for m in meshes]
+    Gblk = [b.block(G, k) for k in range(len(meshes))]
+    gblk = [b.block(g, k, rows=True) for k in range(len(meshes))]
+
+    def fb_batched():
+        fem.assemble_batch(b, meshes, forms, coefs, values, rhs, scatter="coloured")
+        fem.assemble_backward_batch(b, meshes, forms, coefs, G, g, scatter="coloured",
+                                    grad_coef=gcs, grad_coords=gxs)
+
+    def fb_per_mesh():
+        for k in range(len(meshes)):
+            fem.assemble(pats[k], meshes[k], forms[k], coefs[k], vblk[k], rblk[k], scatter="coloured")
+            fem.assemble_backward(pats[k], meshes[k], forms[k], coefs[k], Gblk[k], gblk[k],
+                                  grad_coef=gcs[k], grad_coords=gxs[k], scatter="coloured")
+
+    res = {}
+    for name, fn in (("batched", fb_batched), ("per_mesh_loop", fb_per_mesh)):
+        fn()
+        res[name + "_ms"] = _time_calls(torch, fn, reps)
+        res[name + "_graph_ms"] = _time_calls(torch, graphed(fn), reps)
+    res["speedup_vs_per_mesh_loop"] = res["per_mesh_loop_ms"] / res["batched_graph_ms"]
+    res["speedup_vs_per_mesh_graph"] = res["per_mesh_loop_graph_ms"] / res["batched_graph_ms"]
+    out["fwd_bwd_coloured"] = res
+    for p in pats:
+        p.close()
+    b.close()
     return out
 
 
@@ -120,6 +235,7 @@ def main():
     ap.add_argument("--scatter", default="atomic", choices=["atomic", "coloured"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -191,7 +307,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / 8000.0,
             "traffic": None,
-            "kernel": "k_p1_fwd<3,sinprod,%s>" % args.scatter,
+            "kernel": "k_p1_tile_fwd<3,sinprod,%s>" % ("atomic" if args.scatter == "atomic" else "ordered"),
             "kernel_us": kernel_ms * 1e3,
             "alg_bytes": alg,
         },
@@ -227,6 +343,10 @@ def main():
         extra["bwd_over_fwd"] = bwd_ms / ms_per_step
         extra["bwd_alg_GBps"] = _alg_bytes_bwd(E, N, nnz) / (bwd_ms * 1e-3) / 1e9
         extra["p2_elasticity"] = _bench_p2(torch, fem, meshgen, dev, max(5, args.steps // 3))
+        torch.cuda.empty_cache()
+        if not args.no_batch:
+            extra["batch_512"] = _bench_batch(torch, fem, meshgen, dev, args.steps)
+            torch.cuda.empty_cache()
         out["extra"] = extra
 
     if not args.no_cpu_baseline:

@@ -81,8 +81,17 @@ extern "C" {
                                      scatter is one launch in which every tile waits for its
                                      lower-colour neighbours -- same sums, same bits */
 /* fem_build_pattern: elements per tile of the combined scatter, as log2 in bits 8..11
-   (0 = default 256; accepted 64..1024) */
+   (0 = default: 192 P1 tetrahedra, 256 P1 triangles, 8 P2 tetrahedra; P1 accepts
+   multiples of 64 from 64 to 1024, P2 1 to 64), or for P1 as a count of 64-element
+   wavefronts (1..15) in bits 12..15, which takes precedence */
 #define FEM_TILE_LOG2(k) (((unsigned)(k) & 0xfu) << 8)
+#define FEM_TILE_WAVES(w) (((unsigned)(w) & 0xfu) << 12)
+/* fem_build_pattern: build the P1 tile plan in the input element order.  By default, when
+   the mesh's coordinates are given, P1 tiles are runs of a locality (Morton) order of the
+   element centroids, so that each tile covers a compact group of elements; results are
+   the same sums either way (the coloured variant's summation order follows the plan).
+   P2 tiles always follow the input order. */
+#define FEM_INPUT_ORDER 0x40u
 
 typedef struct fem_pattern fem_pattern; /* opaque, library-owned */
 
@@ -180,6 +189,84 @@ int fem_assemble_backward(const fem_pattern *pattern, const fem_mesh *mesh,
                           const double *grad_values, const double *grad_rhs,
                           double *grad_coef, double *grad_coords, unsigned flags,
                           void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Batched assembly: many independent meshes assembled as one block-diagonal system.
+ * Not in the paper: its per-mesh assembly (Alg. 1, with the elasticity analogue of
+ * Sec. 7) applied to a batch, with one launch per element family (P1 triangles, P1
+ * tetrahedra, P2 tetrahedra) and scatter pass instead of one per mesh.
+ *
+ * Block-diagonal layout.  Mesh k owns the global rows row_offset[k] ..
+ * row_offset[k+1]-1 (its own dof r is global row row_offset[k] + r) and the stored
+ * entries nnz_offset[k] .. nnz_offset[k+1]-1, in the order of its own CSR (as
+ * fem_pattern_export would give it).  Offsets are int64: a batch may store more than
+ * 2^31 - 1 entries; the total row count must fit int32.
+ * ------------------------------------------------------------------------------- */
+typedef struct fem_batch fem_batch; /* opaque, library-owned */
+
+typedef struct {
+    int64_t n_meshes;
+    int64_t n_rows;       /* block-diagonal totals */
+    int64_t nnz;
+    int64_t n_tiles;      /* work items of all families */
+    int32_t n_families;   /* launches per pass in the one-launch scatter modes */
+    int32_t max_colours;  /* largest tile-colour count of a family */
+    int64_t device_bytes; /* device memory held by the handle (patterns included) */
+} fem_batch_info;
+
+/*
+ * Builds the patterns and tile plans of `n_meshes` meshes (as fem_build_pattern, with
+ * ncomp[k] components for mesh k: 1 for P1, 3 for P2) and the batch's work lists.
+ * Every mesh must fit the tile plan (rows of at most 64 (P1) / 128 (P2) nodes).  Meshes
+ * of one family share the tile size, so `flags` (FEM_TILE_LOG2) applies to all.
+ * Synchronises `stream`.  Errors: INVALID_ARG, UNSUPPORTED, INDEX_OVERFLOW, OOM, HIP.
+ */
+int fem_build_batch(const fem_mesh *meshes, const int32_t *ncomp, int64_t n_meshes,
+                    unsigned flags, fem_batch **out, void *stream);
+
+/* Sizes of a batch (host struct; no device work). */
+int fem_batch_query(const fem_batch *batch, fem_batch_info *info);
+
+/* Copies the row and stored-entry offsets (HOST int64 arrays [n_meshes+1]; either may
+ * be NULL). */
+int fem_batch_offsets(const fem_batch *batch, int64_t *row_offset, int64_t *nnz_offset);
+
+/* Writes the block-diagonal CSR: rowptr int64 [n_rows+1], colind int32 [nnz] (global
+ * column = global row of the column dof).  Asynchronous on `stream`. */
+int fem_batch_export(const fem_batch *batch, int64_t *rowptr, int32_t *colind, void *stream);
+
+/*
+ * fem_assemble for every mesh of the batch.  meshes[k], forms[k] and coef[k] (a device
+ * pointer per mesh, layout as for fem_assemble) describe mesh k; P2 meshes take the
+ * elasticity form, P1 meshes the Helmholtz form, and the P1 meshes of one family the
+ * same load kind.  values: double [nnz], rhs: double [n_rows] (may be NULL when no form
+ * has a load), block-diagonal; the rows of a mesh whose form has no load are zeroed.
+ * Flags as for fem_assemble except FEM_ELEMENT_SCATTER; FEM_PREC_FP32 applies to the P2
+ * meshes.
+ * The handle keeps device tables of the per-mesh kernel arguments and uploads them
+ * again (synchronising `stream`) only when the pointers or sizes change, so a repeated
+ * call on the same buffers only launches kernels: it may be captured into a HIP graph
+ * once an identical call has run outside the capture (else UNSUPPORTED).  Calls on one
+ * handle must be ordered on one stream.
+ */
+int fem_assemble_batch(fem_batch *batch, const fem_mesh *meshes, const fem_form *forms,
+                       const double *const *coef, double *values, double *rhs, unsigned flags,
+                       void *stream);
+
+/*
+ * fem_assemble_backward for every mesh of the batch: grad_values [nnz] and grad_rhs
+ * [n_rows] are block-diagonal inputs (either may be NULL); grad_coef[k] and
+ * grad_coords[k] are mesh k's outputs (layouts as for fem_assemble_backward; the arrays
+ * of pointers, or single entries, may be NULL = not requested).  Same table rule as
+ * fem_assemble_batch.
+ */
+int fem_assemble_backward_batch(fem_batch *batch, const fem_mesh *meshes, const fem_form *forms,
+                                const double *const *coef, const double *grad_values,
+                                const double *grad_rhs, double *const *grad_coef,
+                                double *const *grad_coords, unsigned flags, void *stream);
+
+/* Releases a batch and its patterns (NULL is ignored).  Synchronises the device first. */
+void fem_batch_destroy(fem_batch *batch);
 
 /* Static description of a return code. */
 const char *fem_error_string(int code);

@@ -5,12 +5,15 @@ not been built (python -m paper_1802_03433_amd.build).  There is no CPU fallback
 """
 
 from .api import (  # noqa: F401
+    Batch,
     FemAssemble,
     Form,
     Mesh,
     Pattern,
     assemble,
     assemble_backward,
+    assemble_backward_batch,
+    assemble_batch,
     fem_assemble,
 )
 from ._lib import FemError  # noqa: F401

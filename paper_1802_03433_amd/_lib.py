@@ -32,10 +32,26 @@ VALIDATE = 0x4
 ELEMENT_SCATTER = 0x10
 PREC_FP32 = 0x8
 COLOUR_LAUNCHES = 0x20
+INPUT_ORDER = 0x40
 
 
 def TILE_LOG2(k: int) -> int:
     return (int(k) & 0xF) << 8
+
+
+def TILE_WAVES(w: int) -> int:
+    return (int(w) & 0xF) << 12
+
+
+def tile_flags(tile: int) -> int:
+    """Flag bits for a tile of `tile` elements: a power of two, or (P1) a multiple of 64."""
+    tile = int(tile)
+    k = tile.bit_length() - 1
+    if tile > 0 and (1 << k) == tile:
+        return TILE_LOG2(k)
+    if tile % 64 == 0 and 64 <= tile <= 960:
+        return TILE_WAVES(tile // 64)
+    raise ValueError("tile must be a power of two or a multiple of 64 up to 960")
 
 # Every extern "C" function of include/fem.h (checked by the tests).
 EXPORTS = (
@@ -46,6 +62,13 @@ EXPORTS = (
     "fem_pattern_destroy",
     "fem_assemble",
     "fem_assemble_backward",
+    "fem_build_batch",
+    "fem_batch_query",
+    "fem_batch_offsets",
+    "fem_batch_export",
+    "fem_assemble_batch",
+    "fem_assemble_backward_batch",
+    "fem_batch_destroy",
     "fem_error_string",
     "fem_last_error_message",
 )
@@ -90,6 +113,18 @@ class fem_pattern_info(ctypes.Structure):
     ]
 
 
+class fem_batch_info(ctypes.Structure):
+    _fields_ = [
+        ("n_meshes", ctypes.c_int64),
+        ("n_rows", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("n_tiles", ctypes.c_int64),
+        ("n_families", ctypes.c_int32),
+        ("max_colours", ctypes.c_int32),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(
@@ -108,12 +143,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fem_pattern_destroy.restype = None
     L.fem_assemble.argtypes = [P, pm, pf, P, P, P, ctypes.c_uint, P]
     L.fem_assemble_backward.argtypes = [P, pm, pf, P, P, P, P, P, ctypes.c_uint, P]
+    L.fem_build_batch.argtypes = [pm, P, ctypes.c_int64, ctypes.c_uint, ctypes.POINTER(P), P]
+    L.fem_batch_query.argtypes = [P, ctypes.POINTER(fem_batch_info)]
+    L.fem_batch_offsets.argtypes = [P, P, P]
+    L.fem_batch_export.argtypes = [P, P, P, P]
+    L.fem_assemble_batch.argtypes = [P, pm, pf, P, P, P, ctypes.c_uint, P]
+    L.fem_assemble_backward_batch.argtypes = [P, pm, pf, P, P, P, P, P, ctypes.c_uint, P]
+    L.fem_batch_destroy.argtypes = [P]
+    L.fem_batch_destroy.restype = None
     L.fem_error_string.argtypes = [ctypes.c_int]
     L.fem_error_string.restype = ctypes.c_char_p
     L.fem_last_error_message.argtypes = []
     L.fem_last_error_message.restype = ctypes.c_char_p
     for n in ("fem_build_pattern", "fem_pattern_query", "fem_pattern_export",
-              "fem_pattern_colours", "fem_assemble", "fem_assemble_backward"):
+              "fem_pattern_colours", "fem_assemble", "fem_assemble_backward",
+              "fem_build_batch", "fem_batch_query", "fem_batch_offsets", "fem_batch_export",
+              "fem_assemble_batch", "fem_assemble_backward_batch"):
         getattr(L, n).restype = ctypes.c_int
     return L
 

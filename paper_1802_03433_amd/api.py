@@ -109,17 +109,20 @@ class Form:
 class Pattern:
     """Owning wrapper of a fem_pattern handle (sparsity, slot map, colouring)."""
 
-    def __init__(self, mesh: Mesh, ncomp: int = 1, validate: bool = False, tile: int | None = None):
-        """tile: elements per tile of the combined scatter (power of two, 64..1024)."""
+    def __init__(self, mesh: Mesh, ncomp: int = 1, validate: bool = False, tile: int | None = None,
+                 input_order: bool = False):
+        """tile: elements per tile of the combined scatter (P1: multiple of 64, 64..1024;
+        P2: power of two, 1..64).
+        input_order: tiles as runs of the input element order instead of the locality
+        (Morton) order of the element centroids."""
         self.mesh = mesh
         self._h = ctypes.c_void_p()
         ms = mesh.cstruct()
         flags = L.VALIDATE if validate else 0
+        if input_order:
+            flags |= L.INPUT_ORDER
         if tile is not None:
-            k = int(tile).bit_length() - 1
-            if tile <= 0 or (1 << k) != tile:
-                raise ValueError("tile must be a power of two")
-            flags |= L.TILE_LOG2(k)
+            flags |= L.tile_flags(tile)
         rc = L.lib.fem_build_pattern(ctypes.byref(ms), int(ncomp), flags, ctypes.byref(self._h),
                                      _stream_ptr(mesh.coords.device))
         L.check(rc, "fem_build_pattern")
@@ -217,6 +220,138 @@ def assemble_backward(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tens
                                      _flags(scatter, accumulate, False, element_scatter),
                                      _stream_ptr(dev))
     L.check(rc, "fem_assemble_backward")
+    return (grad_coef if want_coef else None), (grad_coords if want_coords else None)
+
+
+class Batch:
+    """Owning wrapper of a fem_batch handle: many meshes, one block-diagonal system.
+
+    Mesh k's rows are row_offset[k] .. row_offset[k+1] and its stored entries
+    nnz_offset[k] .. nnz_offset[k+1] of the batch's values (int64 offsets)."""
+
+    def __init__(self, meshes: list, ncomp: list | None = None, tile: int | None = None):
+        if ncomp is None:
+            ncomp = [3 if m.order == 2 else 1 for m in meshes]
+        self.meshes = list(meshes)
+        n = len(self.meshes)
+        self._h = ctypes.c_void_p()
+        ms = (L.fem_mesh * max(n, 1))(*[m.cstruct() for m in self.meshes])
+        nc = (ctypes.c_int32 * max(n, 1))(*[int(c) for c in ncomp])
+        flags = 0
+        if tile is not None:
+            flags |= L.tile_flags(tile)
+        dev = self.meshes[0].coords.device if n else torch.device("cuda")
+        rc = L.lib.fem_build_batch(ms, nc, n, flags, ctypes.byref(self._h), _stream_ptr(dev))
+        L.check(rc, "fem_build_batch")
+        info = L.fem_batch_info()
+        L.check(L.lib.fem_batch_query(self._h, ctypes.byref(info)), "fem_batch_query")
+        self.n_meshes = int(info.n_meshes)
+        self.n_rows = int(info.n_rows)
+        self.nnz = int(info.nnz)
+        self.n_tiles = int(info.n_tiles)
+        self.n_families = int(info.n_families)
+        self.max_colours = int(info.max_colours)
+        self.device_bytes = int(info.device_bytes)
+        ro = (ctypes.c_int64 * (n + 1))()
+        no = (ctypes.c_int64 * (n + 1))()
+        L.check(L.lib.fem_batch_offsets(self._h, ro, no), "fem_batch_offsets")
+        self.row_offset = [int(v) for v in ro]
+        self.nnz_offset = [int(v) for v in no]
+        self.device = dev
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise ValueError("batch has been closed")
+        return self._h
+
+    def export(self):
+        """Block-diagonal CSR: rowptr int64 [n_rows+1], colind int32 [nnz]."""
+        rowptr = torch.empty(self.n_rows + 1, dtype=torch.int64, device=self.device)
+        colind = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        L.check(L.lib.fem_batch_export(self.handle, _ptr(rowptr), _ptr(colind),
+                                       _stream_ptr(self.device)), "fem_batch_export")
+        return rowptr, colind
+
+    def block(self, t: torch.Tensor, k: int, rows: bool = False) -> torch.Tensor:
+        """Mesh k's slice of a block-diagonal values (or, rows=True, rhs) tensor."""
+        off = self.row_offset if rows else self.nnz_offset
+        return t[off[k]:off[k + 1]]
+
+    def close(self):
+        if self._h:
+            L.lib.fem_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _mesh_array(meshes):
+    n = len(meshes)
+    return (L.fem_mesh * max(n, 1))(*[m.cstruct() for m in meshes])
+
+
+def _form_array(forms):
+    n = len(forms)
+    return (L.fem_form * max(n, 1))(*[f.cstruct() for f in forms])
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * max(len(ts), 1))(*[None if t is None else t.data_ptr() for t in ts])
+
+
+def assemble_batch(batch: Batch, meshes: list, forms: list, coefs: list,
+                   values: torch.Tensor | None = None, rhs: torch.Tensor | None = None,
+                   scatter: str = "atomic", accumulate: bool = False, fp32: bool = False):
+    """fem_assemble_batch; returns block-diagonal (values [nnz], rhs [n_rows] or None)."""
+    n = batch.n_meshes
+    if not (len(meshes) == len(forms) == len(coefs) == n):
+        raise ValueError("one mesh, form and coefficient tensor per batch member")
+    for c in coefs:
+        _need(c, torch.float64, "coef")
+    dev = batch.device
+    if values is None:
+        values = torch.empty(batch.nnz, dtype=torch.float64, device=dev)
+    if rhs is None and any(f.load != "none" for f in forms):
+        rhs = torch.empty(batch.n_rows, dtype=torch.float64, device=dev)
+    _need(values, torch.float64, "values")
+    if rhs is not None:
+        _need(rhs, torch.float64, "rhs")
+    ms, fs, cs = _mesh_array(meshes), _form_array(forms), _ptr_array(coefs)
+    rc = L.lib.fem_assemble_batch(batch.handle, ms, fs, cs, _ptr(values), _ptr(rhs),
+                                  _flags(scatter, accumulate, False, False, fp32), _stream_ptr(dev))
+    L.check(rc, "fem_assemble_batch")
+    return values, rhs
+
+
+def assemble_backward_batch(batch: Batch, meshes: list, forms: list, coefs: list,
+                            grad_values: torch.Tensor | None, grad_rhs: torch.Tensor | None,
+                            want_coef: bool = True, want_coords: bool = True,
+                            scatter: str = "atomic", accumulate: bool = False,
+                            grad_coef: list | None = None, grad_coords: list | None = None):
+    """fem_assemble_backward_batch; returns (list of grad_coef or None, list of
+    grad_coords or None), one entry per mesh."""
+    n = batch.n_meshes
+    if not (len(meshes) == len(forms) == len(coefs) == n):
+        raise ValueError("one mesh, form and coefficient tensor per batch member")
+    for t, nm in ((grad_values, "grad_values"), (grad_rhs, "grad_rhs")):
+        if t is not None:
+            _need(t, torch.float64, nm)
+    if want_coef and grad_coef is None:
+        grad_coef = [torch.empty_like(c) for c in coefs]
+    if want_coords and grad_coords is None:
+        grad_coords = [torch.empty_like(m.coords) for m in meshes]
+    ms, fs, cs = _mesh_array(meshes), _form_array(forms), _ptr_array(coefs)
+    gc = _ptr_array(grad_coef) if want_coef else None
+    gx = _ptr_array(grad_coords) if want_coords else None
+    rc = L.lib.fem_assemble_backward_batch(batch.handle, ms, fs, cs, _ptr(grad_values),
+                                           _ptr(grad_rhs), gc, gx,
+                                           _flags(scatter, accumulate, False), _stream_ptr(batch.device))
+    L.check(rc, "fem_assemble_backward_batch")
     return (grad_coef if want_coef else None), (grad_coords if want_coords else None)
 
 

@@ -1,0 +1,413 @@
+// Batched assembly: many independent meshes assembled into one block-diagonal system
+// with one launch per element family and scatter pass.
+//
+// The batch keeps each mesh's own pattern and tile plan.  Mesh k's dofs are the global
+// rows row_off[k] .. row_off[k+1] and its stored entries the global range nnz_off[k] ..
+// nnz_off[k+1] (int64: a batch may hold more than 2^31 - 1 entries), in its own CSR order.
+// A family's launch walks a list of work items (member << 32) | tile; the member's kernel
+// arguments (pointers with the offsets applied, sizes, tile plan) come from a device table
+// that is rebuilt on the host every call and uploaded only when its bytes change, so
+// repeated calls on the same buffers launch kernels only (and can be graph-captured).
+#include <cstring>
+
+#include "fem_internal.h"
+
+namespace fem {
+
+namespace {
+
+int batch_alloc(fem_batch *b, void **ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(e == hipErrorOutOfMemory ? FEM_ERR_OOM : FEM_ERR_HIP,
+                    std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    b->owned.push_back(DevBuf{*ptr, bytes});
+    b->device_bytes += (int64_t)bytes;
+    return FEM_OK;
+}
+
+int family_of(const fem_pattern *p)
+{
+    if (p->order == 2) return kFamP2;
+    return p->dim == 2 ? kFamP1Tri : kFamP1Tet;
+}
+
+// Work lists, control words and argument tables of one family.
+int build_family(fem_batch *b, BatchFamily &f, hipStream_t s)
+{
+    const size_t nm = f.mesh.size();
+    f.flag_base.assign(nm, 0);
+    std::vector<std::vector<int32_t>> perm(nm);
+    int64_t n = 0;
+    for (size_t j = 0; j < nm; ++j) {
+        const fem_pattern *p = b->pats[f.mesh[j]];
+        if (p->tile != f.T)
+            return fail(FEM_ERR_UNSUPPORTED, "meshes of one family must share the tile size");
+        f.nmax = std::max(f.nmax, p->tile_max_nodes);
+        f.smax = std::max(f.smax, p->tile_max_slots);
+        f.n_colours = std::max(f.n_colours, p->n_tile_colours);
+        f.flag_base[j] = n;
+        n += p->n_tiles;
+        perm[j].resize((size_t)p->n_tiles);
+        if (p->n_tiles > 0)
+            FEM_HIP_TRY(hipMemcpyAsync(perm[j].data(), p->tile_perm, sizeof(int32_t) * p->n_tiles,
+                                       hipMemcpyDeviceToHost, s));
+    }
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    f.n_items = n;
+    if (n >= INT32_MAX) return fail(FEM_ERR_INDEX_OVERFLOW, "too many tiles in one family");
+    std::vector<int64_t> atomic_items, ordered_items;
+    atomic_items.reserve((size_t)n);
+    ordered_items.reserve((size_t)n);
+    for (size_t j = 0; j < nm; ++j) {
+        const fem_pattern *p = b->pats[f.mesh[j]];
+        for (int64_t t = 0; t < p->n_tiles; ++t) atomic_items.push_back(((int64_t)j << 32) | t);
+    }
+    // colour-major: a tile's lower-colour neighbours (same mesh) come before it
+    f.colour_ptr.assign((size_t)f.n_colours + 1, 0);
+    for (int c = 0; c < f.n_colours; ++c) {
+        f.colour_ptr[c] = (int64_t)ordered_items.size();
+        for (size_t j = 0; j < nm; ++j) {
+            const fem_pattern *p = b->pats[f.mesh[j]];
+            if (c >= p->n_tile_colours) continue;
+            for (int64_t i = p->tile_colour_ptr[c]; i < p->tile_colour_ptr[c + 1]; ++i)
+                ordered_items.push_back(((int64_t)j << 32) | perm[j][(size_t)i]);
+        }
+    }
+    f.colour_ptr[f.n_colours] = (int64_t)ordered_items.size();
+    if ((int64_t)ordered_items.size() != n)
+        return fail(FEM_ERR_HIP, "tile colour lists do not cover every tile");
+    void *ptr;
+    FEM_TRY(batch_alloc(b, &ptr, sizeof(int64_t) * (size_t)n));
+    f.items_atomic = (int64_t *)ptr;
+    FEM_TRY(batch_alloc(b, &ptr, sizeof(int64_t) * (size_t)n));
+    f.items_ordered = (int64_t *)ptr;
+    FEM_TRY(batch_alloc(b, &ptr, sizeof(int32_t) * (size_t)(n + 2)));
+    f.ctrl = (int32_t *)ptr;
+    if (n > 0) {
+        FEM_HIP_TRY(hipMemcpyAsync(f.items_atomic, atomic_items.data(), sizeof(int64_t) * n,
+                                   hipMemcpyHostToDevice, s));
+        FEM_HIP_TRY(hipMemcpyAsync(f.items_ordered, ordered_items.data(), sizeof(int64_t) * n,
+                                   hipMemcpyHostToDevice, s));
+    }
+    const size_t arg = (f.kind == kFamP2) ? p2_args_bytes() : p1_tile_args_bytes();
+    f.table_cap = arg * nm;
+    for (int k = 0; k < 2; ++k) {
+        FEM_TRY(batch_alloc(b, &f.table[k], f.table_cap));
+        f.table_host[k].clear();
+    }
+    b->staging_bytes = std::max(b->staging_bytes, f.table_cap);
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    return FEM_OK;
+}
+
+// block-diagonal CSR export
+__global__ void k_shift_rowptr(const int32_t *__restrict__ local, int64_t n_rows, int64_t row0,
+                               int64_t nnz0, int64_t *__restrict__ out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n_rows) out[row0 + r] = nnz0 + local[r];
+}
+
+__global__ void k_shift_colind(int32_t *__restrict__ col, int64_t n, int32_t row0)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) col[i] += row0;
+}
+
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+
+}  // namespace
+
+int batch_table(fem_batch *b, BatchFamily &f, int slot, const void *host, size_t bytes,
+                hipStream_t s, const void **dev)
+{
+    *dev = f.table[slot];
+    std::vector<unsigned char> &cur = f.table_host[slot];
+    if (cur.size() == bytes && std::memcmp(cur.data(), host, bytes) == 0) return FEM_OK;
+    if (bytes > f.table_cap || bytes > b->staging_bytes)
+        return fail(FEM_ERR_INVALID_ARG, "argument table larger than the batch was built for");
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    FEM_HIP_TRY(hipStreamIsCapturing(s, &st));
+    if (st != hipStreamCaptureStatusNone)
+        return fail(FEM_ERR_UNSUPPORTED,
+                    "batched arguments changed under stream capture: make one call with the "
+                    "same buffers before capturing");
+    std::memcpy(b->staging, host, bytes);
+    FEM_HIP_TRY(hipMemcpyAsync(f.table[slot], b->staging, bytes, hipMemcpyHostToDevice, s));
+    FEM_HIP_TRY(hipStreamSynchronize(s));
+    cur.assign((const unsigned char *)host, (const unsigned char *)host + bytes);
+    return FEM_OK;
+}
+
+}  // namespace fem
+
+using namespace fem;
+
+namespace {
+
+int check_batch_meshes(const fem_batch *b, const fem_mesh *meshes, const fem_form *forms)
+{
+    if (!b) return fail(FEM_ERR_INVALID_ARG, "batch is NULL");
+    if (b->n_meshes > 0 && (!meshes || !forms)) return fail(FEM_ERR_INVALID_ARG, "NULL mesh or form array");
+    for (int64_t k = 0; k < b->n_meshes; ++k) {
+        FEM_TRY(check_mesh(&meshes[k], true));
+        FEM_TRY(check_same_mesh(b->pats[k], &meshes[k]));
+        FEM_TRY(check_form(b->pats[k], &forms[k]));
+        const bool elast = forms[k].kind == FEM_FORM_ELASTICITY;
+        if (elast != (b->pats[k]->order == 2))
+            return fail(FEM_ERR_UNSUPPORTED, "a batch assembles elasticity on its P2 meshes and "
+                                             "Helmholtz on its P1 meshes");
+    }
+    return FEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fem_build_batch(const fem_mesh *meshes, const int32_t *ncomp, int64_t n_meshes, unsigned flags,
+                    fem_batch **out, void *stream)
+{
+    clear_error();
+    if (!out) return fail(FEM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_meshes < 0 || (n_meshes > 0 && (!meshes || !ncomp)))
+        return fail(FEM_ERR_INVALID_ARG, "invalid mesh array");
+    if (n_meshes >= ((int64_t)1 << 31)) return fail(FEM_ERR_INDEX_OVERFLOW, "too many meshes");
+    if (flags & FEM_ELEMENT_SCATTER)
+        return fail(FEM_ERR_UNSUPPORTED, "batches are assembled through the tile plan only");
+    hipStream_t s = (hipStream_t)stream;
+    auto *b = new (std::nothrow) fem_batch();
+    if (!b) return fail(FEM_ERR_OOM, "host allocation failed");
+    int rc = FEM_OK;
+    do {
+        if (hipGetDevice(&b->device) != hipSuccess) {
+            rc = fail(FEM_ERR_HIP, "hipGetDevice failed");
+            break;
+        }
+        b->n_meshes = n_meshes;
+        b->pats.assign((size_t)n_meshes, nullptr);
+        b->row_off.assign((size_t)n_meshes + 1, 0);
+        b->nnz_off.assign((size_t)n_meshes + 1, 0);
+        for (int64_t k = 0; k < n_meshes && rc == FEM_OK; ++k) {
+            if (meshes[k].order == 2 && ncomp[k] != 3) {
+                rc = fail(FEM_ERR_UNSUPPORTED, "P2 meshes of a batch take 3-component patterns");
+                break;
+            }
+            rc = fem_build_pattern(&meshes[k], ncomp[k], flags, &b->pats[k], stream);
+            if (rc != FEM_OK) break;
+            const fem_pattern *p = b->pats[k];
+            if (!p->has_tiles && p->n_elems > 0) {
+                rc = fail(FEM_ERR_UNSUPPORTED, "mesh " + std::to_string(k) +
+                                                   " does not fit the tile plan a batch needs");
+                break;
+            }
+            b->row_off[k + 1] = b->row_off[k] + p->n_rows;
+            b->nnz_off[k + 1] = b->nnz_off[k] + p->nnz;
+        }
+        if (rc != FEM_OK) break;
+        if (b->row_off[n_meshes] > INT32_MAX) {
+            rc = fail(FEM_ERR_INDEX_OVERFLOW, "more than 2^31 - 1 rows in one batch");
+            break;
+        }
+        for (int kind : {kFamP2, kFamP1Tet, kFamP1Tri}) {
+            BatchFamily f;
+            f.kind = kind;
+            for (int64_t k = 0; k < n_meshes; ++k)
+                if (b->pats[k]->n_tiles > 0 && family_of(b->pats[k]) == kind) {
+                    f.mesh.push_back((int32_t)k);
+                    if (f.T == 0) f.T = b->pats[k]->tile;
+                }
+            if (f.mesh.empty()) continue;
+            b->fams.push_back(std::move(f));
+        }
+        for (auto &f : b->fams) {
+            rc = build_family(b, f, s);
+            if (rc != FEM_OK) break;
+        }
+        if (rc != FEM_OK) break;
+        if (b->staging_bytes > 0 && hipHostMalloc(&b->staging, b->staging_bytes) != hipSuccess) {
+            b->staging = nullptr;
+            rc = fail(FEM_ERR_OOM, "pinned staging buffer");
+            break;
+        }
+    } while (false);
+    if (rc != FEM_OK) {
+        std::string msg = fem::last_error();
+        fem_batch_destroy(b);
+        set_error(msg);
+        return rc;
+    }
+    *out = b;
+    return FEM_OK;
+}
+
+int fem_batch_query(const fem_batch *b, fem_batch_info *info)
+{
+    clear_error();
+    if (!b || !info) return fail(FEM_ERR_INVALID_ARG, "NULL argument");
+    info->n_meshes = b->n_meshes;
+    info->n_rows = b->row_off[b->n_meshes];
+    info->nnz = b->nnz_off[b->n_meshes];
+    info->n_tiles = 0;
+    info->n_families = (int32_t)b->fams.size();
+    info->max_colours = 0;
+    int64_t bytes = b->device_bytes;
+    for (const auto &f : b->fams) {
+        info->n_tiles += f.n_items;
+        info->max_colours = std::max(info->max_colours, f.n_colours);
+    }
+    for (const fem_pattern *p : b->pats) bytes += p ? p->device_bytes : 0;
+    info->device_bytes = bytes;
+    return FEM_OK;
+}
+
+int fem_batch_offsets(const fem_batch *b, int64_t *row_offset, int64_t *nnz_offset)
+{
+    clear_error();
+    if (!b) return fail(FEM_ERR_INVALID_ARG, "batch is NULL");
+    const size_t n = (size_t)b->n_meshes + 1;
+    if (row_offset) std::memcpy(row_offset, b->row_off.data(), sizeof(int64_t) * n);
+    if (nnz_offset) std::memcpy(nnz_offset, b->nnz_off.data(), sizeof(int64_t) * n);
+    return FEM_OK;
+}
+
+int fem_batch_export(const fem_batch *b, int64_t *rowptr, int32_t *colind, void *stream)
+{
+    clear_error();
+    if (!b || !rowptr) return fail(FEM_ERR_INVALID_ARG, "NULL argument");
+    const int64_t nnz = b->nnz_off[b->n_meshes];
+    if (nnz > 0 && !colind) return fail(FEM_ERR_INVALID_ARG, "colind is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t rmax = 0;
+    for (int64_t k = 0; k < b->n_meshes; ++k) rmax = std::max(rmax, b->pats[k]->n_rows);
+    int32_t *tmp = nullptr;
+    FEM_HIP_TRY(hipMallocAsync((void **)&tmp, sizeof(int32_t) * (size_t)(rmax + 1), s));
+    int rc = FEM_OK;
+    for (int64_t k = 0; k < b->n_meshes && rc == FEM_OK; ++k) {
+        const fem_pattern *p = b->pats[k];
+        rc = fem_pattern_export(p, tmp, colind + b->nnz_off[k], stream);
+        if (rc != FEM_OK) break;
+        if (p->n_rows > 0)
+            hipLaunchKernelGGL(k_shift_rowptr, dim3(grid_for(p->n_rows, 256)), dim3(256), 0, s, tmp,
+                               p->n_rows, b->row_off[k], b->nnz_off[k], rowptr);
+        if (p->nnz > 0 && b->row_off[k] > 0)
+            hipLaunchKernelGGL(k_shift_colind, dim3(grid_for(p->nnz, 256)), dim3(256), 0, s,
+                               colind + b->nnz_off[k], p->nnz, (int32_t)b->row_off[k]);
+    }
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, rowptr + b->row_off[b->n_meshes], nnz);
+    hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(tmp, s);
+    if (rc != FEM_OK) return rc;
+    if (e != hipSuccess) return fail(FEM_ERR_HIP, std::string("batch export: ") + hipGetErrorString(e));
+    return FEM_OK;
+}
+
+int fem_assemble_batch(fem_batch *b, const fem_mesh *meshes, const fem_form *forms,
+                       const double *const *coef, double *values, double *rhs, unsigned flags,
+                       void *stream)
+{
+    clear_error();
+    FEM_TRY(check_batch_meshes(b, meshes, forms));
+    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_PREC_FP32 |
+                  FEM_COLOUR_LAUNCHES))
+        return fail(FEM_ERR_INVALID_ARG, "unknown or unsupported flag bits for a batch");
+    const int64_t nnz = b->nnz_off[b->n_meshes], rows = b->row_off[b->n_meshes];
+    if (!values && nnz > 0) return fail(FEM_ERR_INVALID_ARG, "values is NULL");
+    bool any_load = false;
+    for (int64_t k = 0; k < b->n_meshes; ++k) {
+        if (meshes[k].n_elems > 0 && (!coef || !coef[k]))
+            return fail(FEM_ERR_INVALID_ARG, "coef of mesh " + std::to_string(k) + " is NULL");
+        any_load = any_load || forms[k].load != FEM_LOAD_NONE;
+    }
+    if (any_load && !rhs && rows > 0) return fail(FEM_ERR_INVALID_ARG, "rhs is NULL but a form has a load");
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & FEM_VALIDATE)
+        for (int64_t k = 0; k < b->n_meshes; ++k) FEM_TRY(validate_elements(&meshes[k], s));
+    const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
+    if (!(flags & FEM_ACCUMULATE)) {
+        // the coloured tile scatter stores on its first write of every slot and node row
+        if (!coloured) {
+            FEM_TRY(fill_zero_f64(values, nnz, s));
+            if (rhs) FEM_TRY(fill_zero_f64(rhs, rows, s));
+        } else if (rhs) {
+            // rows no tile writes first: nodes in no element, meshes without a load
+            for (int64_t k = 0; k < b->n_meshes; ++k)
+                if (b->pats[k]->has_isolated_nodes || b->pats[k]->n_elems == 0 ||
+                    forms[k].load == FEM_LOAD_NONE)
+                    FEM_TRY(fill_zero_f64(rhs + b->row_off[k], b->pats[k]->n_rows, s));
+        }
+        if (coloured)
+            for (int64_t k = 0; k < b->n_meshes; ++k)
+                if (b->pats[k]->n_elems == 0) FEM_TRY(fill_zero_f64(values + b->nnz_off[k], b->pats[k]->nnz, s));
+    }
+    BatchIO io;
+    io.values = values;
+    io.rhs = rhs;
+    for (auto &f : b->fams) {
+        if (f.kind == kFamP2) FEM_TRY(p2_tile_batch(b, f, meshes, forms, coef, io, flags, s));
+        else FEM_TRY(p1_tile_batch(b, f, meshes, forms, coef, io, flags, s));
+    }
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+int fem_assemble_backward_batch(fem_batch *b, const fem_mesh *meshes, const fem_form *forms,
+                                const double *const *coef, const double *grad_values,
+                                const double *grad_rhs, double *const *grad_coef,
+                                double *const *grad_coords, unsigned flags, void *stream)
+{
+    clear_error();
+    FEM_TRY(check_batch_meshes(b, meshes, forms));
+    if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_COLOUR_LAUNCHES))
+        return fail(FEM_ERR_INVALID_ARG, "unknown or unsupported flag bits for a batched adjoint");
+    for (int64_t k = 0; k < b->n_meshes; ++k)
+        if (meshes[k].n_elems > 0 && (!coef || !coef[k]))
+            return fail(FEM_ERR_INVALID_ARG, "coef of mesh " + std::to_string(k) + " is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & FEM_VALIDATE)
+        for (int64_t k = 0; k < b->n_meshes; ++k) FEM_TRY(validate_elements(&meshes[k], s));
+    const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
+    if (!(flags & FEM_ACCUMULATE) && grad_coords) {
+        for (int64_t k = 0; k < b->n_meshes; ++k) {
+            const fem_pattern *p = b->pats[k];
+            if (!grad_coords[k]) continue;
+            if (!coloured || p->has_isolated_nodes || p->n_elems == 0)
+                FEM_TRY(fill_zero_f64(grad_coords[k], p->dim * p->n_nodes, s));
+        }
+    }
+    BatchIO io;
+    io.adjoint = true;
+    io.gvalues = grad_values;
+    io.grhs = grad_rhs;
+    io.gcoef = grad_coef;
+    io.gcoords = grad_coords;
+    for (auto &f : b->fams) {
+        if (f.kind == kFamP2) FEM_TRY(p2_tile_batch(b, f, meshes, forms, coef, io, flags, s));
+        else FEM_TRY(p1_tile_batch(b, f, meshes, forms, coef, io, flags, s));
+    }
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+void fem_batch_destroy(fem_batch *b)
+{
+    if (!b) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    for (fem_pattern *p : b->pats) fem_pattern_destroy(p);
+    for (auto &d : b->owned) (void)hipFree(d.ptr);
+    if (b->staging) (void)hipHostFree(b->staging);
+    (void)hipSetDevice(cur);
+    delete b;
+}
+
+}  // extern "C"

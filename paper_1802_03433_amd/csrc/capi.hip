@@ -7,7 +7,7 @@ const char *last_error();
 
 using namespace fem;
 
-namespace {
+namespace fem {
 
 int npe_of(int dim, int order)
 {
@@ -63,7 +63,7 @@ int check_form(const fem_pattern *p, const fem_form *f)
     return fail(FEM_ERR_INVALID_ARG, "unknown form kind");
 }
 
-}  // namespace
+}  // namespace fem
 
 extern "C" {
 
@@ -186,10 +186,13 @@ int fem_pattern_export(const fem_pattern *p, int32_t *rowptr, int32_t *colind, v
 namespace {
 // element colour in scatter order: tile colour, then colour inside the tile
 __global__ void k_tile_elem_colour(const int32_t *__restrict__ tcol, const uint8_t *__restrict__ esub,
-                                   int64_t E, int T, int32_t *__restrict__ out)
+                                   const int32_t *__restrict__ tpos, int64_t E, int T,
+                                   int32_t *__restrict__ out)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < E) out[e] = tcol[e / T] * kMaxSubColours + esub[e];
+    if (e >= E) return;
+    const int64_t pos = tpos ? tpos[e] : e;
+    out[e] = tcol[pos / T] * kMaxSubColours + esub[pos];
 }
 }  // namespace
 
@@ -201,7 +204,7 @@ int fem_pattern_colours(const fem_pattern *p, int32_t *colour, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (p->has_tiles) {
         hipLaunchKernelGGL(k_tile_elem_colour, dim3(grid_for(p->n_elems, 256)), dim3(256), 0, s,
-                           p->tile_colour, p->esub, p->n_elems, p->tile, colour);
+                           p->tile_colour, p->esub, p->tpos, p->n_elems, p->tile, colour);
         FEM_HIP_TRY(hipGetLastError());
     } else {
         FEM_HIP_TRY(hipMemcpyAsync(colour, p->colour, sizeof(int32_t) * p->n_elems,
@@ -284,7 +287,7 @@ int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_
     const bool tiles = p->has_tiles && !(flags & FEM_ELEMENT_SCATTER);
     if (!tiles && coloured && !p->has_element_colouring)
         return fail(FEM_ERR_UNSUPPORTED, "per-element coloured scatter needs an element colouring");
-    if (!accumulate && grad_coords && (!(tiles && coloured) || p->has_isolated_nodes || elast))
+    if (!accumulate && grad_coords && (!(tiles && coloured) || p->has_isolated_nodes))
         FEM_TRY(fill_zero_f64(grad_coords, p->dim * p->n_nodes, s));
     if (!grad_coef && !grad_coords) return FEM_OK;
     const double *grhs = (form->load == FEM_LOAD_NONE) ? nullptr : grad_rhs;

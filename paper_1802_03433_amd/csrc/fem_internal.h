@@ -15,6 +15,7 @@ namespace fem {
 // error state
 // ---------------------------------------------------------------------------------------
 void set_error(const std::string &msg);
+const char *last_error();
 void clear_error();
 
 struct Status {
@@ -40,6 +41,18 @@ inline int fail(int code, const std::string &msg)
 {
     set_error(msg);
     return code;
+}
+
+// ---- scatter modes of the tile kernels -------------------------------------------------
+// kAtomic: device-scope FP64 atomics.  kColoured: one launch per tile colour, plain
+// read-modify-writes.  kOrdered: one launch, tiles in colour order waiting for their
+// lower-colour neighbours, coherent read-modify-writes (same sums as kColoured).
+enum ScatterMode : int { kAtomic = 0, kColoured = 1, kOrdered = 2 };
+
+inline int scatter_mode(unsigned flags)
+{
+    if (!(flags & FEM_SCATTER_COLOURED)) return kAtomic;
+    return (flags & FEM_COLOUR_LAUNCHES) ? kColoured : kOrdered;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -86,7 +99,12 @@ struct fem_pattern {
     bool has_element_colouring = false;
     bool has_isolated_nodes = false;  // nodes in no element (rows left empty)
 
-    // ---- tile plan: consecutive ranges of `tile` elements combined in LDS ----
+    // ---- tile plan: consecutive ranges of `tile` positions combined in LDS ----
+    // Positions follow a locality order of the elements (when coordinates were given at
+    // build time): telem[pos] = element at position pos, tpos = its inverse; NULL means the
+    // input order.  Every per-element array of the plan below is indexed by position.
+    int32_t *telem = nullptr;
+    int32_t *tpos = nullptr;
     bool has_tiles = false;
     int32_t tile = 0;              // elements per tile (= threads per workgroup)
     int64_t n_tiles = 0;
@@ -99,6 +117,11 @@ struct fem_pattern {
     uint64_t *tfirst = nullptr;    // per tile node: bits of trun this tile writes first
                                    // (lowest tile colour among the tiles writing the slot)
     uint8_t *trfirst = nullptr;    // per tile node: 1 if this tile writes the node's RHS first
+    int32_t *tust = nullptr;       // per tile node: offset of its run in its tile's slot list
+    int64_t *tslot_ptr = nullptr;  // [n_tiles+1] offsets into tslot
+    int32_t *tslot = nullptr;      // per tile: distinct slots in node-run order (P1: node-level
+                                   // slot, ~slot when written first; P2: (first << 31) |
+                                   // (tile node << 8) | row position)
     int32_t tile_mw = 1;           // 64-bit mask words per tile node (P1: 1, P2: 2)
     uint16_t *enode16 = nullptr;   // P2: [E][npe] index of conn(e,k) in its tile's node list
     uint8_t *epos8 = nullptr;      // P2: [E][npe*npe] position of conn(e,j) in the row of conn(e,i)
@@ -122,6 +145,67 @@ struct fem_pattern {
 
 namespace fem {
 
+// Element families of a batch; each is one launch per scatter pass.
+enum BatchKind : int { kFamP1Tri = 0, kFamP1Tet = 1, kFamP2 = 2 };
+
+// Meshes of one family in a batch and the work lists of its launches.  A work item is
+// (member << 32) | tile, member = position of the mesh in `mesh`.
+struct BatchFamily {
+    int kind = 0;
+    std::vector<int32_t> mesh;         // batch indices of the members
+    std::vector<int64_t> flag_base;    // per member: offset of its tiles' done flags
+    int64_t n_items = 0;               // tiles of all members
+    int32_t n_colours = 0;             // largest member tile-colour count
+    std::vector<int64_t> colour_ptr;   // host [n_colours+1] ranges of items_ordered
+    int64_t *items_atomic = nullptr;   // device [n_items] member-major
+    int64_t *items_ordered = nullptr;  // device [n_items] colour-major, then member
+    int32_t *ctrl = nullptr;           // device [n_items+2] done flags, ticket, spin failure
+    int32_t T = 0, nmax = 0, smax = 0; // common tile size, largest tile node/slot counts
+    // per-member kernel argument tables, [0] forward and [1] adjoint: device copy and
+    // the host bytes it holds (uploaded again only when they change)
+    void *table[2] = {nullptr, nullptr};
+    size_t table_cap = 0;
+    std::vector<unsigned char> table_host[2];
+};
+
+// Outputs and adjoint inputs of one batched pass.
+struct BatchIO {
+    bool adjoint = false;
+    double *values = nullptr, *rhs = nullptr;            // forward, block-diagonal
+    const double *gvalues = nullptr, *grhs = nullptr;    // adjoint inputs, block-diagonal
+    double *const *gcoef = nullptr;                      // adjoint outputs, per mesh
+    double *const *gcoords = nullptr;
+};
+
+}  // namespace fem
+
+struct fem_batch {
+    int device = 0;
+    int64_t n_meshes = 0;
+    std::vector<fem_pattern *> pats;
+    std::vector<int64_t> row_off, nnz_off;  // host [n_meshes+1]
+    std::vector<fem::BatchFamily> fams;
+    std::vector<fem::DevBuf> owned;
+    int64_t device_bytes = 0;
+    void *staging = nullptr;  // pinned host buffer for table uploads
+    size_t staging_bytes = 0;
+};
+
+namespace fem {
+
+// argument table of a batch family: device pointer of `bytes` host bytes, uploaded on
+// `s` (and `s` synchronised) only when they differ from what the device copy holds
+int batch_table(fem_batch *b, BatchFamily &f, int slot, const void *host, size_t bytes,
+                hipStream_t s, const void **dev);
+// size of one member's kernel arguments
+size_t p1_tile_args_bytes();
+size_t p2_args_bytes();
+// one family's launches of a batched pass
+int p1_tile_batch(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fem_form *forms,
+                  const double *const *coef, const BatchIO &io, unsigned flags, hipStream_t s);
+int p2_tile_batch(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fem_form *forms,
+                  const double *const *coef, const BatchIO &io, unsigned flags, hipStream_t s);
+
 // allocation owned by a pattern
 int pattern_alloc(fem_pattern *p, void **ptr, size_t bytes);
 
@@ -135,8 +219,20 @@ int fill_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 // pattern construction (pattern.hip)
 int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipStream_t s);
 int build_element_colouring(fem_pattern *p, const int32_t *conn, hipStream_t s);
-// tile plan (tiles.hip); returns FEM_ERR_UNSUPPORTED when the mesh does not fit its limits
-int build_tile_plan(fem_pattern *p, const int32_t *conn, int tile, hipStream_t s);
+// Permuted copies of conn ([npe][E]), the slot map ([npe*npe][E]) and the node->element
+// incidence (as positions) for building the tile plan in the locality order (order.hip).
+struct LocalityOrder {
+    int32_t *conn = nullptr, *slot = nullptr, *n2e = nullptr;
+    void release(hipStream_t s);
+};
+// fills p->telem / p->tpos and `o` when the mesh has coordinates (else leaves them NULL)
+int build_locality_order(fem_pattern *p, const fem_mesh *m, LocalityOrder *o, hipStream_t s);
+
+// tile plan (tiles.hip) over element positions: conn, slot map and node->position
+// incidence in position order; returns FEM_ERR_UNSUPPORTED when the mesh does not fit
+// its limits
+int build_tile_plan(fem_pattern *p, const int32_t *conn, const int32_t *slot, const int32_t *n2e,
+                    int tile, hipStream_t s);
 // integer colour sort helpers shared by element and tile colouring (pattern.hip)
 int sort_by_colour(const int32_t *colour, int64_t n, int32_t *perm, std::vector<int64_t> &ptr,
                    hipStream_t s);
@@ -156,6 +252,12 @@ int p1_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
                      const double *coef, const double *gvalues, const double *grhs,
                      double *gcoef, double *gcoords, unsigned flags, hipStream_t s);
 
+// argument checks shared by the C ABI entry points (capi.hip)
+int npe_of(int dim, int order);
+int check_mesh(const fem_mesh *m, bool need_coords);
+int check_same_mesh(const fem_pattern *p, const fem_mesh *m);
+int check_form(const fem_pattern *p, const fem_form *f);
+
 // device check of the element Jacobians (p1.hip; reads the vertex coordinates only)
 int validate_elements(const fem_mesh *m, hipStream_t s);
 
@@ -170,6 +272,44 @@ int p1_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, cons
 inline unsigned grid_for(int64_t n, int threads)
 {
     return (unsigned)((n + threads - 1) / threads);
+}
+
+// Dynamic LDS above 64 KB needs the kernel attribute; set it once per kernel and size
+// (outside any stream capture in practice: the first call of a configuration sets it).
+template <class K>
+void ensure_lds(K kernel, size_t lds)
+{
+    static size_t done = 64 * 1024;
+    if (lds > done) {
+        (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        done = lds;
+    }
+}
+
+// Launches of one batched family pass in its scatter mode.
+template <class K, class A>
+void launch_batch(K kernel, const BatchFamily &f, const A *tab, int mode, int threads, size_t lds,
+                  hipStream_t s)
+{
+    ensure_lds(kernel, lds);
+    if (mode == kAtomic) {
+        hipLaunchKernelGGL(kernel, dim3((unsigned)f.n_items), dim3(threads), lds, s, tab,
+                           (const int64_t *)f.items_atomic, (int32_t *)nullptr);
+        return;
+    }
+    if (mode == kOrdered) {
+        (void)fill_zero_i32(f.ctrl, f.n_items + 2, s);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)f.n_items), dim3(threads), lds, s, tab,
+                           (const int64_t *)f.items_ordered, f.ctrl + f.n_items);
+        return;
+    }
+    for (int c = 0; c < f.n_colours; ++c) {
+        const int64_t b = f.colour_ptr[c], n = f.colour_ptr[c + 1] - b;
+        if (n <= 0) continue;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)n), dim3(threads), lds, s, tab,
+                           (const int64_t *)(f.items_ordered + b), (int32_t *)nullptr);
+    }
 }
 
 }  // namespace fem
@@ -195,7 +335,8 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks)
 // neighbour a tile waits for has already started.  Writes to the outputs use agent-scope
 // (cross-XCD coherent) loads and stores; a tile publishes its done flag after its stores
 // have completed.  The spin is bounded: past the limit the tile records the failure in
-// ctrl[n_tiles + 1] and goes on (wrong sums, never a hang).
+// *err and goes on (wrong sums, never a hang).  `flags` holds one done flag per tile of a
+// mesh; a batched launch gives each mesh its own flags and shares one ticket counter.
 constexpr int kSpinLimit = 1 << 22;
 
 __device__ __forceinline__ double ld_coherent(const double *p)
@@ -208,22 +349,22 @@ __device__ __forceinline__ void st_coherent(double *p, double v)
 }
 
 // thread 0 takes the next ticket; every thread returns it
-__device__ __forceinline__ int64_t take_ticket(int32_t *ctrl, int64_t n_tiles, int *sh)
+__device__ __forceinline__ int64_t take_ticket(int32_t *counter, int *sh)
 {
-    if (threadIdx.x == 0) *sh = atomicAdd(ctrl + n_tiles, 1);
+    if (threadIdx.x == 0) *sh = atomicAdd(counter, 1);
     __syncthreads();
     return *sh;
 }
 
 __device__ __forceinline__ void wait_preds(const int32_t *pred_ptr, const int32_t *pred,
-                                           int32_t *ctrl, int64_t n_tiles, int64_t tile)
+                                           int32_t *flags, int32_t *err, int64_t tile)
 {
     for (int32_t k = pred_ptr[tile] + threadIdx.x; k < pred_ptr[tile + 1]; k += blockDim.x) {
-        int32_t *flag = ctrl + pred[k];
+        int32_t *flag = flags + pred[k];
         int spins = 0;
         while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
             if (++spins > kSpinLimit) {
-                atomicOr(ctrl + n_tiles + 1, 1);
+                atomicOr(err, 1);
                 break;
             }
             __builtin_amdgcn_s_sleep(2);
@@ -255,14 +396,24 @@ __device__ __forceinline__ void ordered_rmw(double *out, int n, SlotF slot, ValF
     }
 }
 
-__device__ __forceinline__ void publish_done(int32_t *ctrl, int64_t tile)
+// Index of this workgroup's work item: its ticket (ordered), its block (one launch per
+// colour) or its XCD-remapped block (atomic)
+template <int MODE>
+__device__ __forceinline__ int64_t launch_index(int32_t *counter, int *sh)
+{
+    if (MODE == kOrdered) return take_ticket(counter, sh);
+    if (MODE == kColoured) return blockIdx.x;
+    return xcd_block(blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void publish_done(int32_t *flags, int64_t tile)
 {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);  // this lane's coherent stores have completed
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __syncthreads();
     if (threadIdx.x == 0)
-        __hip_atomic_store(ctrl + tile, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(flags + tile, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace fem

@@ -1,0 +1,161 @@
+// Locality order of the elements for the tile plan.
+//
+// A tile is a run of consecutive positions of this order.  In the input order (for the
+// structured meshes: cell after cell along x) a tile of 256 tetrahedra is a strip of 43
+// cells; sorted by the Z-order (Morton) code of their centroids, the same 256 elements
+// form a compact block, with fewer distinct nodes and CSR slots to stage and update per
+// tile.  The order is a schedule only: results are the same sums (the coloured variant's
+// summation order changes with it, deterministically).
+#include <hipcub/hipcub.hpp>
+
+#include "fem_internal.h"
+
+namespace fem {
+
+namespace {
+
+constexpr int kOT = 256;
+
+// bits of v (10 bits) spread to every third position
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// bits of v (15 bits) spread to every second position
+__device__ __forceinline__ uint32_t spread2(uint32_t v)
+{
+    v &= 0x7fffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+// Morton code of each element's vertex centroid on a 2^10 (3D) / 2^15 (2D) grid over the
+// bounding box bb = [lo_0..lo_{d-1}, hi_0..hi_{d-1}]
+__global__ void k_morton(const double *__restrict__ coords, int64_t N, const int32_t *__restrict__ conn,
+                         int64_t E, int dim, int nv, const double *__restrict__ bb,
+                         uint32_t *__restrict__ key, int32_t *__restrict__ idx)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int bits = (dim == 3) ? 10 : 15;
+    const double cells = (double)(1u << bits);
+    uint32_t q[3] = {0u, 0u, 0u};
+    for (int d = 0; d < dim; ++d) {
+        double c = 0.0;
+        for (int v = 0; v < nv; ++v) c += coords[d * N + conn[(int64_t)v * E + e]];
+        c /= nv;
+        const double ext = bb[dim + d] - bb[d];
+        const double t = ext > 0.0 ? (c - bb[d]) / ext * cells : 0.0;
+        q[d] = (uint32_t)fmin(cells - 1.0, fmax(0.0, t));  // NaN maps to 0
+    }
+    key[e] = (dim == 3) ? (spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2))
+                        : (spread2(q[0]) | (spread2(q[1]) << 1));
+    idx[e] = (int32_t)e;
+}
+
+__global__ void k_inverse(const int32_t *__restrict__ perm, int64_t E, int32_t *__restrict__ inv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < E) inv[perm[i]] = (int32_t)i;
+}
+
+// out[r][i] = in[r][perm[i]] for rows r < rows
+__global__ void k_gather_rows(const int32_t *__restrict__ in, int64_t E, int rows,
+                              const int32_t *__restrict__ perm, int32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= E) return;
+    const int64_t src = perm[i];
+    for (int r = 0; r < rows; ++r) out[(int64_t)r * E + i] = in[(int64_t)r * E + src];
+}
+
+__global__ void k_map_through(const int32_t *__restrict__ in, int64_t n, const int32_t *__restrict__ inv,
+                              int32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = inv[in[i]];
+}
+
+}  // namespace
+
+int build_locality_order(fem_pattern *p, const fem_mesh *m, LocalityOrder *o, hipStream_t s)
+{
+    const int64_t E = p->n_elems, N = p->n_nodes;
+    const int dim = p->dim, nv = p->dim + 1, npe = p->npe;
+    o->release(s);
+    if (E == 0 || !m->coords) return FEM_OK;
+    if (E > INT32_MAX) return fail(FEM_ERR_INDEX_OVERFLOW, "element count exceeds int32");
+    // bounding box of the coordinates
+    double *bb = nullptr;
+    void *scratch = nullptr;
+    size_t sbytes = 0, need = 0;
+    FEM_HIP_TRY(hipMallocAsync((void **)&bb, sizeof(double) * 2 * dim, s));
+    for (int d = 0; d < dim; ++d) {
+        FEM_HIP_TRY(hipcub::DeviceReduce::Min(nullptr, need, m->coords + d * N, bb + d, (int)N, s));
+        sbytes = std::max(sbytes, need);
+        FEM_HIP_TRY(hipcub::DeviceReduce::Max(nullptr, need, m->coords + d * N, bb + dim + d, (int)N, s));
+        sbytes = std::max(sbytes, need);
+    }
+    uint32_t *key = nullptr, *key2 = nullptr;
+    int32_t *idx = nullptr;
+    FEM_HIP_TRY(hipMallocAsync((void **)&key, sizeof(uint32_t) * E, s));
+    FEM_HIP_TRY(hipMallocAsync((void **)&key2, sizeof(uint32_t) * E, s));
+    FEM_HIP_TRY(hipMallocAsync((void **)&idx, sizeof(int32_t) * E, s));
+    FEM_TRY(pattern_alloc(p, (void **)&p->telem, sizeof(int32_t) * E));
+    FEM_TRY(pattern_alloc(p, (void **)&p->tpos, sizeof(int32_t) * E));
+    FEM_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, need, key, key2, idx, p->telem, (int)E,
+                                                   0, 32, s));
+    sbytes = std::max(sbytes, need);
+    FEM_HIP_TRY(hipMallocAsync(&scratch, sbytes, s));
+    for (int d = 0; d < dim; ++d) {
+        need = sbytes;
+        FEM_HIP_TRY(hipcub::DeviceReduce::Min(scratch, need, m->coords + d * N, bb + d, (int)N, s));
+        need = sbytes;
+        FEM_HIP_TRY(hipcub::DeviceReduce::Max(scratch, need, m->coords + d * N, bb + dim + d, (int)N, s));
+    }
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(E, kOT)), dim3(kOT), 0, s, m->coords, N, m->conn, E,
+                       dim, nv, bb, key, idx);
+    // stable radix sort: equal codes keep ascending element order (deterministic)
+    need = sbytes;
+    FEM_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(scratch, need, key, key2, idx, p->telem, (int)E,
+                                                   0, 32, s));
+    hipLaunchKernelGGL(k_inverse, dim3(grid_for(E, kOT)), dim3(kOT), 0, s, p->telem, E, p->tpos);
+    // permuted connectivity and slot map, incidence as positions
+    const int64_t EK = E * npe;
+    FEM_HIP_TRY(hipMallocAsync((void **)&o->conn, sizeof(int32_t) * EK, s));
+    FEM_HIP_TRY(hipMallocAsync((void **)&o->slot, sizeof(int32_t) * EK * npe, s));
+    FEM_HIP_TRY(hipMallocAsync((void **)&o->n2e, sizeof(int32_t) * EK, s));
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(E, kOT)), dim3(kOT), 0, s, m->conn, E, npe,
+                       p->telem, o->conn);
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(E, kOT)), dim3(kOT), 0, s, p->slot, E, npe * npe,
+                       p->telem, o->slot);
+    hipLaunchKernelGGL(k_map_through, dim3(grid_for(EK, kOT)), dim3(kOT), 0, s, p->n2e, EK, p->tpos,
+                       o->n2e);
+    hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(scratch, s);
+    (void)hipFreeAsync(bb, s);
+    (void)hipFreeAsync(key, s);
+    (void)hipFreeAsync(key2, s);
+    (void)hipFreeAsync(idx, s);
+    if (e != hipSuccess) return fail(FEM_ERR_HIP, std::string("locality order: ") + hipGetErrorString(e));
+    return FEM_OK;
+}
+
+void LocalityOrder::release(hipStream_t s)
+{
+    if (conn) (void)hipFreeAsync(conn, s);
+    if (slot) (void)hipFreeAsync(slot, s);
+    if (n2e) (void)hipFreeAsync(n2e, s);
+    conn = slot = n2e = nullptr;
+}
+
+}  // namespace fem

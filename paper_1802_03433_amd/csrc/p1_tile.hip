@@ -12,6 +12,8 @@
 //   C  one global update per distinct slot and node, coalesced (the slot list is sorted):
 //      device-scope FP64 atomics, or -- colour by colour -- plain stores (first writer of
 //      a slot) and read-modify-writes.
+#include <cstring>
+
 #include "fem_internal.h"
 #include "quadrature.h"
 
@@ -19,29 +21,25 @@ namespace fem {
 
 namespace {
 
-// kAtomic: device-scope FP64 atomics.  kColoured: one launch per tile colour, plain
-// read-modify-writes.  kOrdered: one launch, tiles in colour order waiting for their
-// lower-colour neighbours, coherent read-modify-writes (same sums as kColoured).
-enum Mode : int { kAtomic = 0, kColoured = 1, kOrdered = 2 };
-
 struct TileArgs {
     const double *coords;
     int64_t N, E;
     int T;
-    const int32_t *rowptr;
     const int32_t *tnode_ptr;
     const int32_t *tnode;
     const uint64_t *trun;
-    const uint64_t *tfirst;
     const uint8_t *trfirst;
     const uint64_t *enode;
     const uint32_t *epos;
     const uint8_t *esub;
     const int32_t *tile_nsub;
+    const int32_t *telem;  // element at each position (NULL: positions are elements)
+    const int32_t *tust;
+    const int64_t *tslot_ptr;
+    const int32_t *tslot;
     const int32_t *tile_list;  // coloured: tiles of the launched colour; ordered: all, by colour
     const int32_t *pred_ptr, *pred;
-    int32_t *ctrl;
-    int64_t n_tiles;
+    int32_t *flags, *counter, *err;  // ordered scatter: done flags, ticket counter, spin failure
     const double *kappa;
     double c, fconst;
     int nmax, smax;
@@ -65,7 +63,6 @@ struct Lds {
     int32_t *ust;  // [nmax]     first slot of each node's run
     int32_t *us;   // [smax]     slot list (~slot marks a first writer)
     int32_t *nd;   // [nmax]     node ids
-    int32_t *scan; // [blockDim]
     uint8_t *nf;   // [nmax]     node first-writer flags
     __device__ Lds(unsigned char *base, int nmax, int smax)
     {
@@ -77,8 +74,7 @@ struct Lds {
         ust = (int32_t *)(rb + nmax);
         us = ust + nmax;
         nd = us + smax;
-        scan = nd + nmax;
-        nf = (uint8_t *)(scan + 1024);
+        nf = (uint8_t *)(nd + nmax);
     }
 };
 
@@ -86,48 +82,25 @@ template <int D>
 size_t lds_bytes(int nmax, int smax)
 {
     return sizeof(double) * (size_t)(2 * D * nmax + smax + nmax) + sizeof(uint64_t) * nmax +
-           sizeof(int32_t) * (size_t)(nmax + smax + nmax + 1024) + (size_t)nmax + 16;
+           sizeof(int32_t) * (size_t)(nmax + smax + nmax) + (size_t)nmax + 16;
 }
 
-// Exclusive scan over the workgroup: shuffle scan inside each wavefront, wave totals
-// through LDS (blockDim is a multiple of 64).
-__device__ int wg_scan_excl(int v, int *sh, int *total)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) sh[w] = x;
-    __syncthreads();
-    int base = 0, tot = 0;
-    for (int i = 0; i < nw; ++i) {
-        int t = sh[i];
-        base += (i < w) ? t : 0;
-        tot += t;
-    }
-    *total = tot;
-    __syncthreads();
-    return base + x - v;
-}
-
-// Phase A.  Returns the number of distinct slots of the tile.
+// Phase A: the tile's nodes (coordinates, row masks, run offsets) and its distinct-slot
+// list, both precomputed in the plan and loaded coalesced.  Returns the number of distinct
+// slots.  slot_first keeps the first-writer marks (~slot) of the list; the adjoint gathers
+// the upstream gradient of every slot.
 template <int D>
 __device__ int stage_tile(const TileArgs &a, Lds<D> &L, int64_t tile, int nn, bool slot_first,
                           bool gather_grad)
 {
     const int n0 = a.tnode_ptr[tile];
-    const int bd = blockDim.x;
-    const int per = (nn + bd - 1) / bd;
-    const int k0 = min(nn, (int)threadIdx.x * per), k1 = min(nn, k0 + per);
-    int local = 0;
-    for (int k = k0; k < k1; ++k) {
-        int32_t n = a.tnode[n0 + k];
-        uint64_t r = a.trun[n0 + k];
+    const int64_t s0 = a.tslot_ptr[tile];
+    const int ns = (int)(a.tslot_ptr[tile + 1] - s0);
+    for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+        const int32_t n = a.tnode[n0 + k];
         L.nd[k] = n;
-        L.rb[k] = r;
+        L.rb[k] = a.trun[n0 + k];
+        L.ust[k] = a.tust[n0 + k];
         L.nf[k] = a.use_first ? a.trfirst[n0 + k] : 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -135,36 +108,15 @@ __device__ int stage_tile(const TileArgs &a, Lds<D> &L, int64_t tile, int nn, bo
             L.nacc[d * a.nmax + k] = 0.0;
         }
         if (gather_grad) L.gr[k] = a.grhs ? a.grhs[n] : 0.0;
-        local += __popcll(r);
     }
-    int total = 0;
-    int off = wg_scan_excl(local, L.scan, &total);
-    {
-        // slot_first: mark the slots this tile writes first (forward, coloured); the
-        // adjoint gathers through the list and must see plain slot numbers
-        for (int k = k0; k < k1; ++k) {
-            L.ust[k] = off;
-            uint64_t r = L.rb[k];
-            uint64_t f = slot_first ? a.tfirst[n0 + k] : 0ull;
-            int32_t base = a.rowptr[L.nd[k]];
-            while (r) {
-                int b = __builtin_ctzll(r);
-                int32_t slot = base + b;
-                L.us[off] = ((f >> b) & 1ull) ? ~slot : slot;
-                L.sacc[off] = 0.0;
-                ++off;
-                r &= r - 1;
-            }
-        }
+    for (int u = threadIdx.x; u < ns; u += blockDim.x) {
+        const int32_t sl = a.tslot[s0 + u];
+        const int32_t plain = sl < 0 ? ~sl : sl;
+        L.us[u] = slot_first ? sl : plain;
+        L.sacc[u] = (gather_grad && a.gvalues) ? a.gvalues[plain] : 0.0;
     }
     __syncthreads();
-    if (gather_grad) {
-        // gathered upstream gradient of every distinct slot, coalesced
-        for (int u = threadIdx.x; u < total; u += bd)
-            L.sacc[u] = a.gvalues ? a.gvalues[L.us[u]] : 0.0;
-        __syncthreads();
-    }
-    return total;
+    return ns;
 }
 
 template <int D>
@@ -240,17 +192,12 @@ __device__ __forceinline__ void qpoint(const Elem<D> &g, int q, double *xq)
 }
 
 template <int D, int LOAD, int MODE>
-__global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
+__device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
 {
     constexpr int NP = D + 1;
     using R = quad::P1Rule<D>;
     extern __shared__ __align__(16) unsigned char smem[];
     Lds<D> L(smem, a.nmax, a.smax);
-    __shared__ int s_ticket;
-    int64_t tile;
-    if (MODE == kOrdered) tile = a.tile_list[take_ticket(a.ctrl, a.n_tiles, &s_ticket)];
-    else if (MODE == kColoured) tile = a.tile_list[blockIdx.x];
-    else tile = xcd_block(blockIdx.x, gridDim.x);
     const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];
     const int64_t e0 = tile * a.T;
     const int ne = (int)min((int64_t)a.T, a.E - e0);
@@ -265,7 +212,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
         en = a.enode[e];
 #pragma unroll
         for (int i = 0; i < NP; ++i) pr[i] = a.epos[i * a.E + e];
-        kap = a.kappa[e];
+        kap = a.kappa[a.telem ? a.telem[e] : e];
         if (MODE != kAtomic) sc = a.esub[e];
     }
     const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false);
@@ -348,7 +295,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
     }
     __syncthreads();
     if (MODE == kOrdered) {
-        wait_preds(a.pred_ptr, a.pred, a.ctrl, a.n_tiles, tile);
+        wait_preds(a.pred_ptr, a.pred, a.flags, a.err, tile);
         ordered_rmw<8>(
             a.values, ns, [&](int u) { const int32_t s = L.us[u]; return s < 0 ? ~s : s; },
             [&](int u) { return L.sacc[u]; }, [&](int u) { return L.us[u] < 0; });
@@ -356,7 +303,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
             ordered_rmw<4>(
                 a.rhs, nn, [&](int k) { return L.nd[k]; }, [&](int k) { return L.nacc[k]; },
                 [&](int k) { return L.nf[k] != 0; });
-        publish_done(a.ctrl, tile);
+        publish_done(a.flags, tile);
         return;
     }
     for (int u = threadIdx.x; u < ns; u += blockDim.x) {
@@ -381,17 +328,12 @@ __global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
 // once into LDS; per element dL/dkappa (stored directly) and the vertex gradients
 // (accumulated per tile node in LDS, then one global update per node and axis).
 template <int D, int LOAD, int MODE>
-__global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
+__device__ __forceinline__ void p1_bwd_tile(const TileArgs &a, int64_t tile)
 {
     constexpr int NP = D + 1;
     using R = quad::P1Rule<D>;
     extern __shared__ __align__(16) unsigned char smem[];
     Lds<D> L(smem, a.nmax, a.smax);
-    __shared__ int s_ticket;
-    int64_t tile;
-    if (MODE == kOrdered) tile = a.tile_list[take_ticket(a.ctrl, a.n_tiles, &s_ticket)];
-    else if (MODE == kColoured) tile = a.tile_list[blockIdx.x];
-    else tile = xcd_block(blockIdx.x, gridDim.x);
     const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];
     const int64_t e0 = tile * a.T;
     const int ne = (int)min((int64_t)a.T, a.E - e0);
@@ -401,11 +343,13 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
     uint32_t pr[NP];
     double kap = 0.0;
     int sc = 0;
+    int64_t eu = e;  // the element at position e
     if (active) {
         en = a.enode[e];
 #pragma unroll
         for (int i = 0; i < NP; ++i) pr[i] = a.epos[i * a.E + e];
-        kap = a.kappa[e];
+        if (a.telem) eu = a.telem[e];
+        kap = a.kappa[eu];
         if (MODE != kAtomic) sc = a.esub[e];
     }
     stage_tile<D>(a, L, tile, nn, false, true);
@@ -445,8 +389,8 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
             }
         if (a.gkappa) {
             const double dk = g.vol * s;
-            if (a.accumulate) a.gkappa[e] += dk;
-            else a.gkappa[e] = dk;
+            if (a.accumulate) a.gkappa[eu] += dk;
+            else a.gkappa[eu] = dk;
         }
 #pragma unroll
         for (int k = 0; k < NP; ++k)
@@ -515,7 +459,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
             }
     }
     if (!a.gcoords) {  // uniform: no coordinate gradient wanted
-        if (MODE == kOrdered) publish_done(a.ctrl, tile);
+        if (MODE == kOrdered) publish_done(a.flags, tile);
         return;
     }
     if (MODE == kAtomic) {
@@ -539,12 +483,12 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
     }
     __syncthreads();
     if (MODE == kOrdered) {
-        wait_preds(a.pred_ptr, a.pred, a.ctrl, a.n_tiles, tile);
+        wait_preds(a.pred_ptr, a.pred, a.flags, a.err, tile);
         ordered_rmw<4>(
             a.gcoords, D * nn, [&](int t) { return (t / nn) * a.N + L.nd[t % nn]; },
             [&](int t) { return L.nacc[(t / nn) * a.nmax + t % nn]; },
             [&](int t) { return L.nf[t % nn] != 0; });
-        publish_done(a.ctrl, tile);
+        publish_done(a.flags, tile);
         return;
     }
     for (int k = threadIdx.x; k < nn; k += blockDim.x) {
@@ -560,24 +504,67 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
     }
 }
 
+// One mesh: the work item is a tile (through the colour-ordered list unless atomic).
+template <int D, int LOAD, int MODE>
+__global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
+{
+    __shared__ int s_ticket;
+    const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
+    p1_fwd_tile<D, LOAD, MODE>(a, MODE == kAtomic ? i : a.tile_list[i]);
+}
+
+template <int D, int LOAD, int MODE>
+__global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
+{
+    __shared__ int s_ticket;
+    const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
+    p1_bwd_tile<D, LOAD, MODE>(a, MODE == kAtomic ? i : a.tile_list[i]);
+}
+
+// A batch of meshes: the work item (mesh << 32) | tile comes from the launch's item list
+// and the mesh's arguments from a device table.
+template <int D, int LOAD, int MODE>
+__global__ __launch_bounds__(1024) void k_p1_tile_fwd_batch(const TileArgs *__restrict__ tab,
+                                                            const int64_t *__restrict__ items,
+                                                            int32_t *counter)
+{
+    __shared__ int s_ticket;
+    const int64_t w = items[launch_index<MODE>(counter, &s_ticket)];
+    p1_fwd_tile<D, LOAD, MODE>(tab[w >> 32], w & 0xffffffffll);
+}
+
+template <int D, int LOAD, int MODE>
+__global__ __launch_bounds__(1024) void k_p1_tile_bwd_batch(const TileArgs *__restrict__ tab,
+                                                            const int64_t *__restrict__ items,
+                                                            int32_t *counter)
+{
+    __shared__ int s_ticket;
+    const int64_t w = items[launch_index<MODE>(counter, &s_ticket)];
+    p1_bwd_tile<D, LOAD, MODE>(tab[w >> 32], w & 0xffffffffll);
+}
+
 template <int D>
 TileArgs base_args(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef)
 {
-    TileArgs a{};
+    // all bytes zero, padding included: batched calls compare argument tables bytewise
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.coords = m->coords;
     a.N = m->n_nodes;
     a.E = m->n_elems;
     a.T = p->tile;
-    a.rowptr = p->rowptr_n;
     a.tnode_ptr = p->tnode_ptr;
     a.tnode = p->tnode;
     a.trun = p->trun;
-    a.tfirst = p->tfirst;
     a.trfirst = p->trfirst;
     a.enode = p->enode;
     a.epos = p->epos;
     a.esub = p->esub;
     a.tile_nsub = p->tile_nsub;
+    a.telem = p->telem;
+    a.tust = p->tust;
+    a.tslot_ptr = p->tslot_ptr;
+    a.tslot = p->tslot;
     a.kappa = coef;
     a.c = f->reaction;
     a.fconst = f->load_const[0];
@@ -585,17 +572,16 @@ TileArgs base_args(const fem_pattern *p, const fem_mesh *m, const fem_form *f, c
     a.smax = p->tile_max_slots;
     a.pred_ptr = p->tpred_ptr;
     a.pred = p->tpred;
-    a.ctrl = p->tctrl;
-    a.n_tiles = p->n_tiles;
+    a.flags = p->tctrl;
+    a.counter = p->tctrl + p->n_tiles;
+    a.err = p->tctrl + p->n_tiles + 1;
     return a;
 }
 
 template <class K>
 void launch(K kernel, const fem_pattern *p, TileArgs a, int mode, size_t lds, hipStream_t s)
 {
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
+    ensure_lds(kernel, lds);
     if (mode == kAtomic) {
         a.tile_list = nullptr;
         hipLaunchKernelGGL(kernel, dim3((unsigned)p->n_tiles), dim3(p->tile), lds, s, a);
@@ -657,13 +643,80 @@ int bwd_load(const fem_pattern *p, const TileArgs &a, int load, int mode, hipStr
     }
 }
 
-int scatter_mode(unsigned flags)
+template <int D, int LOAD>
+void batch_launch(const BatchFamily &f, const TileArgs *t, bool adj, int mode, size_t lds,
+                  hipStream_t s)
 {
-    if (!(flags & FEM_SCATTER_COLOURED)) return kAtomic;
-    return (flags & FEM_COLOUR_LAUNCHES) ? kColoured : kOrdered;
+    if (adj) {
+        if (mode == kOrdered) launch_batch(k_p1_tile_bwd_batch<D, LOAD, kOrdered>, f, t, mode, f.T, lds, s);
+        else if (mode == kColoured) launch_batch(k_p1_tile_bwd_batch<D, LOAD, kColoured>, f, t, mode, f.T, lds, s);
+        else launch_batch(k_p1_tile_bwd_batch<D, LOAD, kAtomic>, f, t, mode, f.T, lds, s);
+    } else {
+        if (mode == kOrdered) launch_batch(k_p1_tile_fwd_batch<D, LOAD, kOrdered>, f, t, mode, f.T, lds, s);
+        else if (mode == kColoured) launch_batch(k_p1_tile_fwd_batch<D, LOAD, kColoured>, f, t, mode, f.T, lds, s);
+        else launch_batch(k_p1_tile_fwd_batch<D, LOAD, kAtomic>, f, t, mode, f.T, lds, s);
+    }
+}
+
+template <int D>
+int batch_d(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fem_form *forms,
+            const double *const *coef, const BatchIO &io, unsigned flags, hipStream_t s)
+{
+    const int mode = scatter_mode(flags);
+    const bool acc = (flags & FEM_ACCUMULATE) != 0;
+    std::vector<TileArgs> tab(f.mesh.size());
+    int load = -1;
+    for (size_t j = 0; j < f.mesh.size(); ++j) {
+        const int k = f.mesh[j];
+        TileArgs a = base_args<D>(b->pats[k], &meshes[k], &forms[k], coef[k]);
+        a.flags = f.ctrl + f.flag_base[j];
+        a.counter = f.ctrl + f.n_items;
+        a.err = f.ctrl + f.n_items + 1;
+        a.tile_list = nullptr;
+        a.use_first = mode != kAtomic && !acc;
+        int lk;
+        if (io.adjoint) {
+            a.gvalues = io.gvalues ? io.gvalues + b->nnz_off[k] : nullptr;
+            a.grhs = (io.grhs && forms[k].load != FEM_LOAD_NONE) ? io.grhs + b->row_off[k] : nullptr;
+            a.gkappa = io.gcoef ? io.gcoef[k] : nullptr;
+            a.gcoords = io.gcoords ? io.gcoords[k] : nullptr;
+            a.accumulate = acc;
+            lk = a.grhs ? forms[k].load : FEM_LOAD_NONE;
+        } else {
+            a.values = io.values + b->nnz_off[k];
+            a.rhs = (io.rhs && forms[k].load != FEM_LOAD_NONE) ? io.rhs + b->row_off[k] : nullptr;
+            lk = a.rhs ? forms[k].load : FEM_LOAD_NONE;
+        }
+        if (load < 0) load = lk;
+        else if (load != lk)
+            return fail(FEM_ERR_UNSUPPORTED, "the P1 meshes of a batch must share the load kind");
+        std::memcpy(&tab[j], &a, sizeof(TileArgs));
+    }
+    const void *dev = nullptr;
+    FEM_TRY(batch_table(b, f, io.adjoint ? 1 : 0, tab.data(), sizeof(TileArgs) * tab.size(), s, &dev));
+    const TileArgs *t = (const TileArgs *)dev;
+    const size_t lds = lds_bytes<D>(f.nmax, f.smax);
+    if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
+    switch (load) {
+    case FEM_LOAD_NONE: batch_launch<D, FEM_LOAD_NONE>(f, t, io.adjoint, mode, lds, s); break;
+    case FEM_LOAD_CONST: batch_launch<D, FEM_LOAD_CONST>(f, t, io.adjoint, mode, lds, s); break;
+    default: batch_launch<D, FEM_LOAD_SINPROD>(f, t, io.adjoint, mode, lds, s); break;
+    }
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
 }
 
 }  // namespace
+
+size_t p1_tile_args_bytes() { return sizeof(TileArgs); }
+
+int p1_tile_batch(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fem_form *forms,
+                  const double *const *coef, const BatchIO &io, unsigned flags, hipStream_t s)
+{
+    if (f.n_items == 0) return FEM_OK;
+    return f.kind == kFamP1Tri ? batch_d<2>(b, f, meshes, forms, coef, io, flags, s)
+                               : batch_d<3>(b, f, meshes, forms, coef, io, flags, s);
+}
 
 int p1_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,
                     double *values, double *rhs, unsigned flags, hipStream_t s)

@@ -18,6 +18,8 @@
 // atomics, or colour by colour with stores (first writer) and read-modify-writes.  The
 // dof-level slot of (3n+a, 3m+b), m at position p of node row n (length L), is
 // 9 rowptr[n] + 3 a L + 3 p + b.
+#include <cstring>
+
 #include "fem_internal.h"
 #include "quadrature.h"
 
@@ -25,7 +27,6 @@ namespace fem {
 
 namespace {
 
-enum Mode : int { kAtomic = 0, kColoured = 1, kOrdered = 2 };
 constexpr int kP2Threads = 256;  // four wavefronts
 constexpr int NPE = 10;
 
@@ -82,83 +83,68 @@ struct P2Args {
     const int32_t *tnode_ptr;
     const int32_t *tnode;
     const uint64_t *trun;    // 2 words per tile node
-    const uint64_t *tfirst;  // 2 words per tile node
+    const int32_t *tust;     // per tile node: offset of its run in the tile's pair list
+    const int64_t *tslot_ptr;
+    const int32_t *tslot;    // per tile: pair codes (first << 31) | (tile node << 8) | position
     const uint8_t *trfirst;
     const uint16_t *enode;  // [E][10] tile-node index of each local node
     const uint8_t *epos;    // [E][100] row position of each local pair
+    const int32_t *telem;   // element at each position (NULL: positions are elements)
     const int32_t *tile_list;
     const int32_t *pred_ptr, *pred;
-    int32_t *ctrl;
-    int64_t n_tiles;
+    int32_t *flags, *counter, *err;  // ordered scatter: done flags, ticket counter, spin failure
     const double *lam, *mu;
     int load;
     double bf[3];
     double *values, *rhs;
+    // adjoint
+    const double *gvalues, *grhs;
+    double *gcoef, *gcoords;
+    bool accumulate;
     int nmax, smax;
     bool use_first;
 };
 
-// LDS carve-up
+// LDS carve-up (the adjoint needs no Gram buffers but per-node coordinate accumulators)
 struct P2Lds {
     double *R;      // [14][10][3] reference gradients
-    double *G;      // [4][32][32] Gram matrices of the wavefronts' current elements
-    double *acc;    // [smax][9] pair accumulators
+    double *G;      // [4][32][32] Gram matrices of the wavefronts' current elements (forward)
+    double *acc;    // [smax][9] pair accumulators (forward) / gathered grad_values (adjoint)
     double *xs;     // [3][nmax]
-    double *racc;   // [3][nmax]
+    double *racc;   // [3][nmax] rhs accumulators (forward) / gathered grad_rhs (adjoint)
+    double *xacc;   // [3][nmax] adjoint: coordinate-gradient accumulators
     uint64_t *rb;   // [nmax][2]
     int32_t *ust;   // [nmax]
     int32_t *rp;    // [nmax]
     int32_t *rl;    // [nmax]
     int32_t *nd;    // [nmax]
     int32_t *us;    // [smax]  (first << 31) | (node << 8) | position
-    int32_t *scan;  // [16]
     uint16_t *lp;   // [T][100] pair index of (element, i, j)
     uint8_t *nf;    // [nmax]
-    __device__ P2Lds(unsigned char *b, int nmax, int smax, int T)
+    __device__ P2Lds(unsigned char *b, int nmax, int smax, int T, bool adj)
     {
         R = (double *)b;
         G = R + 14 * 10 * 3;
-        acc = G + 4 * 32 * 32;
+        acc = G + (adj ? 0 : 4 * 32 * 32);
         xs = acc + 9 * smax;
         racc = xs + 3 * nmax;
-        rb = (uint64_t *)(racc + 3 * nmax);
+        xacc = racc + 3 * nmax;
+        rb = (uint64_t *)(xacc + (adj ? 3 * nmax : 0));
         ust = (int32_t *)(rb + 2 * nmax);
         rp = ust + nmax;
         rl = rp + nmax;
         nd = rl + nmax;
         us = nd + nmax;
-        scan = us + smax;
-        lp = (uint16_t *)(scan + 16);
+        lp = (uint16_t *)(us + smax);
         nf = (uint8_t *)(lp + T * 100);
     }
 };
 
-size_t p2_lds_bytes(int nmax, int smax, int T)
+size_t p2_lds_bytes(int nmax, int smax, int T, bool adj)
 {
-    return sizeof(double) * (size_t)(420 + 4 * 1024 + 9 * smax + 6 * nmax) + sizeof(uint64_t) * 2 * nmax +
-           sizeof(int32_t) * (size_t)(4 * nmax + smax + 16) + sizeof(uint16_t) * 100 * T + nmax + 16;
-}
-
-__device__ int wg_scan_excl(int v, int *sh, int *total)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) sh[w] = x;
-    __syncthreads();
-    int base = 0, tot = 0;
-    for (int i = 0; i < nw; ++i) {
-        int t = sh[i];
-        base += (i < w) ? t : 0;
-        tot += t;
-    }
-    *total = tot;
-    __syncthreads();
-    return base + x - v;
+    return sizeof(double) * (size_t)(420 + (adj ? 0 : 4 * 1024) + 9 * smax + (adj ? 9 : 6) * nmax) +
+           sizeof(uint64_t) * 2 * nmax +
+           sizeof(int32_t) * (size_t)(4 * nmax + smax) + sizeof(uint16_t) * 100 * T + nmax + 16;
 }
 
 __device__ __forceinline__ int popc_below(const uint64_t *m, int p)
@@ -203,63 +189,75 @@ __device__ __forceinline__ double pval(const double *R, int q, int c, const doub
     return r[0] * inv[0][a] + r[1] * inv[1][a] + r[2] * inv[2][a];
 }
 
-template <int MODE, bool F32>
-__global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    P2Lds L(smem, a.nmax, a.smax, a.T);
-    __shared__ int s_ticket;
-    const int tid = threadIdx.x;
-    int64_t tile;
-    if (MODE == kOrdered) tile = a.tile_list[take_ticket(a.ctrl, a.n_tiles, &s_ticket)];
-    else if (MODE == kColoured) tile = a.tile_list[blockIdx.x];
-    else tile = xcd_block(blockIdx.x, gridDim.x);
-    const int n0 = a.tnode_ptr[tile];
-    const int nn = a.tnode_ptr[tile + 1] - n0;
-    const int64_t e0 = tile * a.T;
-    const int ne = (int)min((int64_t)a.T, a.E - e0);
+// The 9 * total values of a tile's distinct node pairs are numbered t = (a * total + u) * 3
+// + b (row component a, pair u, column component b), so that consecutive t of one node row
+// are consecutive in memory.  Their LDS accumulators are acc[9 u + 3 a + b].
+struct PairValue {
+    int u, ra, cb;
+    __device__ PairValue(int t, int total)
+    {
+        ra = t / (3 * total);
+        const int rest = t - ra * 3 * total;
+        u = rest / 3;
+        cb = rest - 3 * u;
+    }
+};
 
-    // ---- stage: reference gradients (scaled by sqrt(w_q)), tile nodes, distinct pairs ----
+__device__ __forceinline__ int64_t pair_slot(const P2Lds &L, const PairValue &v)
+{
+    const int32_t code = L.us[v.u];
+    const int k = (code >> 8) & 0xffff, p = code & 0xff;
+    return 9 * (int64_t)L.rp[k] + 3 * (int64_t)v.ra * L.rl[k] + 3 * p + v.cb;
+}
+
+// Phase A of both kernels: reference gradients (scaled by sqrt(w_q)), the tile's nodes,
+// its distinct node pairs and the pair index of every (element, i, j).  The forward
+// clears the pair and node accumulators; the adjoint gathers grad_values and grad_rhs
+// into them (coalesced) and clears the coordinate-gradient accumulators.  Returns the
+// number of distinct pairs.
+__device__ int p2_stage(const P2Args &a, P2Lds &L, int64_t tile, int n0, int nn, int64_t e0,
+                        int ne, bool adj)
+{
+    const int tid = threadIdx.x;
     for (int t = tid; t < 14 * 10 * 3; t += kP2Threads) {
         const int q = t / 30, i = (t / 3) % 10, m = t % 3;
         L.R[t] = sqrt(quad::Tet14::w(q)) * ref_grad(q, i, m);
     }
-    const int per = (nn + kP2Threads - 1) / kP2Threads;
-    const int k0 = min(nn, tid * per), k1 = min(nn, k0 + per);
-    int local = 0;
-    for (int k = k0; k < k1; ++k) {
+    const int64_t s0 = a.tslot_ptr[tile];
+    const int total = (int)(a.tslot_ptr[tile + 1] - s0);
+    for (int k = tid; k < nn; k += kP2Threads) {
         const int32_t n = a.tnode[n0 + k];
         L.nd[k] = n;
         L.rb[2 * k] = a.trun[2 * (int64_t)(n0 + k)];
         L.rb[2 * k + 1] = a.trun[2 * (int64_t)(n0 + k) + 1];
+        L.ust[k] = a.tust[n0 + k];
         L.rp[k] = a.rowptr[n];
         L.rl[k] = a.rowptr[n + 1] - a.rowptr[n];
         L.nf[k] = a.use_first ? a.trfirst[n0 + k] : 0;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             L.xs[d * a.nmax + k] = a.coords[d * a.N + n];
-            L.racc[d * a.nmax + k] = 0.0;
-        }
-        local += __popcll(L.rb[2 * k]) + __popcll(L.rb[2 * k + 1]);
-    }
-    int total = 0;
-    int off = wg_scan_excl(local, L.scan, &total);
-    for (int k = k0; k < k1; ++k) {
-        L.ust[k] = off;
-        for (int w = 0; w < 2; ++w) {
-            uint64_t r = L.rb[2 * k + w];
-            const uint64_t f = a.use_first ? a.tfirst[2 * (int64_t)(n0 + k) + w] : 0ull;
-            while (r) {
-                const int b = __builtin_ctzll(r);
-                L.us[off] = (((f >> b) & 1ull) ? (int32_t)0x80000000 : 0) | (k << 8) | (64 * w + b);
-#pragma unroll
-                for (int v = 0; v < 9; ++v) L.acc[9 * off + v] = 0.0;
-                ++off;
-                r &= r - 1;
+            if (adj) {
+                L.racc[d * a.nmax + k] = a.grhs ? a.grhs[3 * (int64_t)n + d] : 0.0;
+                L.xacc[d * a.nmax + k] = 0.0;
+            } else {
+                L.racc[d * a.nmax + k] = 0.0;
             }
         }
     }
+    for (int u = tid; u < total; u += kP2Threads) {
+        const int32_t code = a.tslot[s0 + u];
+        L.us[u] = a.use_first ? code : (code & 0x7fffffff);
+    }
+    if (!adj)
+        for (int t = tid; t < 9 * total; t += kP2Threads) L.acc[t] = 0.0;
     __syncthreads();
+    if (adj) {
+        for (int t = tid; t < 9 * total; t += kP2Threads) {
+            const PairValue v(t, total);
+            L.acc[9 * v.u + 3 * v.ra + v.cb] = a.gvalues ? a.gvalues[pair_slot(L, v)] : 0.0;
+        }
+    }
     for (int t = tid; t < ne * 100; t += kP2Threads) {
         const int el = t / 100, ij = t - 100 * el, i = ij / 10;
         const int64_t e = e0 + el;
@@ -268,6 +266,21 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
         L.lp[el * 100 + ij] = (uint16_t)(L.ust[ki] + popc_below(&L.rb[2 * ki], p));
     }
     __syncthreads();
+    return total;
+}
+
+template <int MODE, bool F32>
+__device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    P2Lds L(smem, a.nmax, a.smax, a.T, false);
+    const int tid = threadIdx.x;
+    const int n0 = a.tnode_ptr[tile];
+    const int nn = a.tnode_ptr[tile + 1] - n0;
+    const int64_t e0 = tile * a.T;
+    const int ne = (int)min((int64_t)a.T, a.E - e0);
+
+    const int total = p2_stage(a, L, tile, n0, nn, e0, ne, false);
 
     // ---- elements: one per wavefront, four in flight ----
     const int wave = tid >> 6, lane = tid & 63;
@@ -288,8 +301,9 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
             double inv[3][3];
             p2_geometry(x, inv, vol);
             const double sv = sqrt(vol);
-            lm = a.lam[e];
-            mm = a.mu[e];
+            const int64_t eu = a.telem ? a.telem[e] : e;
+            lm = a.lam[eu];
+            mm = a.mu[eu];
             // G = P^T P, symmetric: output tiles (0,0), (0,1), (1,1); (1,0) by transposition
             const int lo = lane & 15, hi = lane >> 4;
 #pragma unroll
@@ -400,38 +414,28 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
     // ---- one global update per distinct (pair, a, b) and per (node, a) ----
     const int nvals = 9 * total;
     if (MODE == kOrdered) {
-        wait_preds(a.pred_ptr, a.pred, a.ctrl, a.n_tiles, tile);
-        auto slot_of = [&](int t) {
-            const int ra = t / (3 * total), rest = t - ra * 3 * total;
-            const int u = rest / 3, cb = rest - 3 * (rest / 3);
-            const int32_t code = L.us[u];
-            const int k = (code >> 8) & 0xffff, p = code & 0xff;
-            return 9 * (int64_t)L.rp[k] + 3 * (int64_t)ra * L.rl[k] + 3 * p + cb;
-        };
+        wait_preds(a.pred_ptr, a.pred, a.flags, a.err, tile);
+        auto slot_of = [&](int t) { return pair_slot(L, PairValue(t, total)); };
         auto val_of = [&](int t) {
-            const int ra = t / (3 * total), rest = t - ra * 3 * total;
-            const int u = rest / 3, cb = rest - 3 * (rest / 3);
-            return L.acc[9 * u + 3 * ra + cb];
+            const PairValue v(t, total);
+            return L.acc[9 * v.u + 3 * v.ra + v.cb];
         };
-        auto first_of = [&](int t) { return L.us[(t - (t / (3 * total)) * 3 * total) / 3] < 0; };
+        auto first_of = [&](int t) { return L.us[PairValue(t, total).u] < 0; };
         ordered_rmw<8>(a.values, nvals, slot_of, val_of, first_of);
         if (a.load == FEM_LOAD_CONST)
             ordered_rmw<4>(
                 a.rhs, 3 * nn, [&](int t) { return 3 * (int64_t)L.nd[t / 3] + t % 3; },
                 [&](int t) { return L.racc[(t % 3) * a.nmax + t / 3]; },
                 [&](int t) { return L.nf[t / 3] != 0; });
-        publish_done(a.ctrl, tile);
+        publish_done(a.flags, tile);
         return;
     }
     for (int t = tid; t < nvals; t += kP2Threads) {
-        const int ra = t / (3 * total), rest = t - ra * 3 * total;
-        const int u = rest / 3, cb = rest - 3 * (rest / 3);
-        const int32_t code = L.us[u];
-        const int k = (code >> 8) & 0xffff, p = code & 0xff;
-        const int64_t slot = 9 * (int64_t)L.rp[k] + 3 * (int64_t)ra * L.rl[k] + 3 * p + cb;
-        const double v = L.acc[9 * u + 3 * ra + cb];
+        const PairValue pv(t, total);
+        const int64_t slot = pair_slot(L, pv);
+        const double v = L.acc[9 * pv.u + 3 * pv.ra + pv.cb];
         if (MODE == kAtomic) unsafeAtomicAdd(a.values + slot, v);
-        else if (code < 0) a.values[slot] = v;
+        else if (L.us[pv.u] < 0) a.values[slot] = v;
         else a.values[slot] += v;
     }
     if (a.load == FEM_LOAD_CONST) {
@@ -446,12 +450,237 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
     }
 }
 
+
+// Entries (r, s) of S_lam = Gb + Gb^T and S_mu = W_mu + W_mu^T for one element, where Gb
+// is the element's block of grad_values and W_mu[(i,a),(j,b)] = Gb[(i,b),(j,a)] +
+// delta_ab sum_c Gb[(i,c),(j,c)] is the adjoint of the mu part of K; zero in the padding.
+__device__ __forceinline__ void s_entries(const double *acc, const uint16_t *lpe, int r, int c,
+                                          double &sl, double &sm)
+{
+    if (r >= 30 || c >= 30) {
+        sl = 0.0;
+        sm = 0.0;
+        return;
+    }
+    const int i = r / 3, a = r - 3 * i, j = c / 3, b = c - 3 * j;
+    const double *gij = acc + 9 * lpe[10 * i + j];
+    const double *gji = acc + 9 * lpe[10 * j + i];
+    sl = gij[3 * a + b] + gji[3 * b + a];
+    sm = gij[3 * b + a] + gji[3 * a + b];
+    if (a == b) sm += (gij[0] + gij[4] + gij[8]) + (gji[0] + gji[4] + gji[8]);
+}
+
+// Adjoint of the elasticity assembly for L = <grad_values, values> + <grad_rhs, rhs>.
+// Per element, with P the scaled gradient matrix of the forward (G = P^T P):
+//   dL/dlam = <Gb, G> = 1/2 sum (P S_lam) o P,   dL/dmu = <W_mu, G> = 1/2 sum (P S_mu) o P,
+// both products on the matrix cores (2 x 2 output tiles, 8 steps of K = 4).  Through the
+// geometry, Pb = dL/dP = lam P S_lam + mu P S_mu gives C = inv^T dL/dinv with
+// C[a][c] = sum_{q,i} P[q][(i,a)] Pb[q][(i,c)], and with L_vol = |T| dL/d|T| (the matrix
+// part is linear in |T|: lam dL/dlam + mu dL/dmu; the body force adds its own term)
+//   dL/dJ = (L_vol I - C) inv^T,  x_{m+1} += dL/dJ[:, m],  x_0 -= sum_m dL/dJ[:, m].
+// Edge nodes sit at the midpoints and are not read: they receive no gradient.
+template <int MODE>
+__device__ __forceinline__ void p2_bwd_tile(const P2Args &a, int64_t tile)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    P2Lds L(smem, a.nmax, a.smax, a.T, true);
+    const int tid = threadIdx.x;
+    const int n0 = a.tnode_ptr[tile];
+    const int nn = a.tnode_ptr[tile + 1] - n0;
+    const int64_t e0 = tile * a.T;
+    const int ne = (int)min((int64_t)a.T, a.E - e0);
+
+    p2_stage(a, L, tile, n0, nn, e0, ne, true);
+
+    const int wave = tid >> 6, lane = tid & 63, lo = lane & 15, hi = lane >> 4;
+    const bool body = a.load == FEM_LOAD_CONST && a.grhs != nullptr;
+    for (int base = 0; base < ne; base += 4) {
+        const int el = base + wave;
+        const bool has = el < ne;
+        // red: dL/dlam, dL/dmu (both x2), C[3][3], body-force part of L_vol
+        double red[12];
+#pragma unroll
+        for (int v = 0; v < 12; ++v) red[v] = 0.0;
+        double inv[3][3], vol = 0.0, lm = 0.0, mm = 0.0;
+        int vnode[4] = {0, 0, 0, 0};
+        if (has) {
+            const int64_t e = e0 + el;
+            double x[4][3];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                vnode[v] = a.enode[e * NPE + v];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) x[v][d] = L.xs[d * a.nmax + vnode[v]];
+            }
+            p2_geometry(x, inv, vol);
+            const double sv = sqrt(vol);
+            const int64_t eu = a.telem ? a.telem[e] : e;
+            lm = a.lam[eu];
+            mm = a.mu[eu];
+            if (a.gvalues) {
+                const uint16_t *lpe = L.lp + el * 100;
+                d4_t yl[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+                d4_t ym[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll 2
+                for (int ks = 0; ks < 8; ++ks) {
+                    // A = P (16 x 32): lane holds P[lo][4 ks + hi]; B = S: lane holds
+                    // S[4 ks + hi][16 cb + lo]
+                    const int k = 4 * ks + hi;
+                    const double av = sv * pval(L.R, lo, k, inv);
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        double sl, sm;
+                        s_entries(L.acc, lpe, k, 16 * cb + lo, sl, sm);
+                        yl[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sl, yl[cb], 0, 0, 0);
+                        ym[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sm, ym[cb], 0, 0, 0);
+                    }
+                }
+                // output: register r of lane l holds row (l / 16) + 4 r, column l % 16
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll 2
+                    for (int r = 0; r < 4; ++r) {
+                        const int q = hi + 4 * r, c = 16 * cb + lo;
+                        if (q < 14 && c < 30) {
+                            const int i = c / 3, cc = c - 3 * i;
+                            double pa[3];
+#pragma unroll
+                            for (int t = 0; t < 3; ++t) pa[t] = sv * pval(L.R, q, 3 * i + t, inv);
+                            const double p = pa[cc];
+                            red[0] += yl[cb][r] * p;
+                            red[1] += ym[cb][r] * p;
+                            const double pb = lm * yl[cb][r] + mm * ym[cb][r];
+#pragma unroll
+                            for (int t = 0; t < 3; ++t) red[2 + 3 * t + cc] += pa[t] * pb;
+                        }
+                    }
+            }
+            if (body && lane < NPE) {
+                // body force: b[(i,c)] = f_c |T| (1/|T|) int phi_i, linear in |T|
+                const int kn = a.enode[e * NPE + lane];
+                double gb = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gb += L.racc[c * a.nmax + kn] * a.bf[c];
+                red[11] = vol * phi_mean(lane) * gb;
+            }
+        }
+        // wavefront sums (every lane ends with the totals)
+#pragma unroll
+        for (int v = 0; v < 12; ++v) {
+            double x = red[v];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+            red[v] = x;
+        }
+        const double dl = 0.5 * red[0], dm = 0.5 * red[1];
+        if (has && lane == 0 && a.gcoef) {
+            const int64_t e = a.telem ? a.telem[e0 + el] : e0 + el;
+            if (a.accumulate) {
+                a.gcoef[e] += dl;
+                a.gcoef[a.E + e] += dm;
+            } else {
+                a.gcoef[e] = dl;
+                a.gcoef[a.E + e] = dm;
+            }
+        }
+        // lanes 0..11: (component, vertex) of the element's coordinate gradient
+        double xb = 0.0;
+        int xk = 0, xd = 0;
+        if (has && a.gcoords && lane < 12) {
+            const double lvol = lm * dl + mm * dm + red[11];
+            const int d = lane / 4, v = lane - 4 * d;
+            // dL/dJ[d][m] = sum_c (L_vol delta_dc - C[d][c]) inv[m][c]
+            auto jbar = [&](int m) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    s += ((d == c ? lvol : 0.0) - red[2 + 3 * d + c]) * inv[m][c];
+                return s;
+            };
+            if (v == 0) xb = -(jbar(0) + jbar(1) + jbar(2));
+            else xb = jbar(v - 1);
+            xk = vnode[v];
+            xd = d;
+        }
+        if (a.gcoords) {
+            if (MODE == kAtomic) {
+                if (has && lane < 12) atomicAdd(&L.xacc[xd * a.nmax + xk], xb);
+            } else {
+                // deterministic: the four elements are added in element order
+                for (int w2 = 0; w2 < 4; ++w2) {
+                    if (wave == w2 && has && lane < 12) L.xacc[xd * a.nmax + xk] += xb;
+                    __syncthreads();
+                }
+            }
+        }
+    }
+    if (!a.gcoords) {
+        if (MODE == kOrdered) publish_done(a.flags, tile);
+        return;
+    }
+    __syncthreads();
+    if (MODE == kOrdered) {
+        wait_preds(a.pred_ptr, a.pred, a.flags, a.err, tile);
+        ordered_rmw<4>(
+            a.gcoords, 3 * nn, [&](int t) { return (t / nn) * a.N + L.nd[t % nn]; },
+            [&](int t) { return L.xacc[(t / nn) * a.nmax + t % nn]; },
+            [&](int t) { return L.nf[t % nn] != 0; });
+        publish_done(a.flags, tile);
+        return;
+    }
+    for (int t = tid; t < 3 * nn; t += kP2Threads) {
+        const int d = t / nn, k = t - d * nn;
+        double *dst = a.gcoords + d * a.N + L.nd[k];
+        const double v = L.xacc[d * a.nmax + k];
+        if (MODE == kAtomic) unsafeAtomicAdd(dst, v);
+        else if (L.nf[k]) *dst = v;
+        else *dst += v;
+    }
+}
+
+// One mesh: the work item is a tile (through the colour-ordered list unless atomic).
+template <int MODE, bool F32>
+__global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
+{
+    __shared__ int s_ticket;
+    const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
+    p2_fwd_tile<MODE, F32>(a, MODE == kAtomic ? i : a.tile_list[i]);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kP2Threads) void k_p2_tile_bwd(P2Args a)
+{
+    __shared__ int s_ticket;
+    const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
+    p2_bwd_tile<MODE>(a, MODE == kAtomic ? i : a.tile_list[i]);
+}
+
+// A batch of meshes: the work item (mesh << 32) | tile comes from the launch's item list
+// and the mesh's arguments from a device table.
+template <int MODE, bool F32>
+__global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd_batch(const P2Args *__restrict__ tab,
+                                                                  const int64_t *__restrict__ items,
+                                                                  int32_t *counter)
+{
+    __shared__ int s_ticket;
+    const int64_t w = items[launch_index<MODE>(counter, &s_ticket)];
+    p2_fwd_tile<MODE, F32>(tab[w >> 32], w & 0xffffffffll);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kP2Threads) void k_p2_tile_bwd_batch(const P2Args *__restrict__ tab,
+                                                                  const int64_t *__restrict__ items,
+                                                                  int32_t *counter)
+{
+    __shared__ int s_ticket;
+    const int64_t w = items[launch_index<MODE>(counter, &s_ticket)];
+    p2_bwd_tile<MODE>(tab[w >> 32], w & 0xffffffffll);
+}
+
 template <class K>
 void p2_launch(K kernel, const fem_pattern *p, P2Args a, int mode, size_t lds, hipStream_t s)
 {
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
+    ensure_lds(kernel, lds);
     if (mode == kAtomic) {
         a.tile_list = nullptr;
         hipLaunchKernelGGL(kernel, dim3((unsigned)p->n_tiles), dim3(kP2Threads), lds, s, a);
@@ -473,13 +702,13 @@ void p2_launch(K kernel, const fem_pattern *p, P2Args a, int mode, size_t lds, h
 
 }  // namespace
 
-int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,
-                    double *values, double *rhs, unsigned flags, hipStream_t s)
+namespace {
+
+P2Args p2_args(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef)
 {
-    if (p->n_tiles == 0) return FEM_OK;
-    const int mode = !(flags & FEM_SCATTER_COLOURED) ? kAtomic
-                     : ((flags & FEM_COLOUR_LAUNCHES) ? kColoured : kOrdered);
-    P2Args a{};
+    // all bytes zero, padding included: batched calls compare argument tables bytewise
+    P2Args a;
+    std::memset(&a, 0, sizeof(a));
     a.coords = m->coords;
     a.N = m->n_nodes;
     a.E = m->n_elems;
@@ -488,25 +717,98 @@ int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
     a.tnode_ptr = p->tnode_ptr;
     a.tnode = p->tnode;
     a.trun = p->trun;
-    a.tfirst = p->tfirst;
+    a.tust = p->tust;
+    a.tslot_ptr = p->tslot_ptr;
+    a.tslot = p->tslot;
     a.trfirst = p->trfirst;
     a.enode = p->enode16;
     a.epos = p->epos8;
+    a.telem = p->telem;
     a.pred_ptr = p->tpred_ptr;
     a.pred = p->tpred;
-    a.ctrl = p->tctrl;
-    a.n_tiles = p->n_tiles;
+    a.flags = p->tctrl;
+    a.counter = p->tctrl + p->n_tiles;
+    a.err = p->tctrl + p->n_tiles + 1;
     a.lam = coef;
     a.mu = coef + m->n_elems;
-    a.load = rhs ? f->load : FEM_LOAD_NONE;
     for (int c = 0; c < 3; ++c) a.bf[c] = f->load_const[c];
-    a.values = values;
-    a.rhs = rhs;
     a.nmax = p->tile_max_nodes;
     a.smax = p->tile_max_slots;
+    return a;
+}
+
+template <bool F32>
+void p2_batch_fwd(const BatchFamily &f, const P2Args *t, int mode, size_t lds, hipStream_t s)
+{
+    if (mode == kOrdered) launch_batch(k_p2_tile_fwd_batch<kOrdered, F32>, f, t, mode, kP2Threads, lds, s);
+    else if (mode == kColoured) launch_batch(k_p2_tile_fwd_batch<kColoured, F32>, f, t, mode, kP2Threads, lds, s);
+    else launch_batch(k_p2_tile_fwd_batch<kAtomic, F32>, f, t, mode, kP2Threads, lds, s);
+}
+
+}  // namespace
+
+size_t p2_args_bytes() { return sizeof(P2Args); }
+
+int p2_tile_batch(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fem_form *forms,
+                  const double *const *coef, const BatchIO &io, unsigned flags, hipStream_t s)
+{
+    if (f.n_items == 0) return FEM_OK;
+    if (f.T > 64) return fail(FEM_ERR_UNSUPPORTED, "P2 tiles hold at most 64 elements");
+    const int mode = scatter_mode(flags);
+    const bool acc = (flags & FEM_ACCUMULATE) != 0;
+    std::vector<P2Args> tab(f.mesh.size());
+    for (size_t j = 0; j < f.mesh.size(); ++j) {
+        const int k = f.mesh[j];
+        P2Args a = p2_args(b->pats[k], &meshes[k], &forms[k], coef[k]);
+        a.flags = f.ctrl + f.flag_base[j];
+        a.counter = f.ctrl + f.n_items;
+        a.err = f.ctrl + f.n_items + 1;
+        a.tile_list = nullptr;
+        a.use_first = mode != kAtomic && !acc;
+        if (io.adjoint) {
+            a.gvalues = io.gvalues ? io.gvalues + b->nnz_off[k] : nullptr;
+            a.grhs = (io.grhs && forms[k].load != FEM_LOAD_NONE) ? io.grhs + b->row_off[k] : nullptr;
+            a.load = a.grhs ? forms[k].load : FEM_LOAD_NONE;
+            a.gcoef = io.gcoef ? io.gcoef[k] : nullptr;
+            a.gcoords = io.gcoords ? io.gcoords[k] : nullptr;
+            a.accumulate = acc;
+        } else {
+            a.values = io.values + b->nnz_off[k];
+            a.rhs = (io.rhs && forms[k].load != FEM_LOAD_NONE) ? io.rhs + b->row_off[k] : nullptr;
+            a.load = a.rhs ? forms[k].load : FEM_LOAD_NONE;
+        }
+        std::memcpy(&tab[j], &a, sizeof(P2Args));
+    }
+    const void *dev = nullptr;
+    FEM_TRY(batch_table(b, f, io.adjoint ? 1 : 0, tab.data(), sizeof(P2Args) * tab.size(), s, &dev));
+    const P2Args *t = (const P2Args *)dev;
+    const size_t lds = p2_lds_bytes(f.nmax, f.smax, f.T, io.adjoint);
+    if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "P2 tile needs more LDS than a CU has");
+    if (io.adjoint) {
+        if (mode == kOrdered) launch_batch(k_p2_tile_bwd_batch<kOrdered>, f, t, mode, kP2Threads, lds, s);
+        else if (mode == kColoured) launch_batch(k_p2_tile_bwd_batch<kColoured>, f, t, mode, kP2Threads, lds, s);
+        else launch_batch(k_p2_tile_bwd_batch<kAtomic>, f, t, mode, kP2Threads, lds, s);
+    } else if (flags & FEM_PREC_FP32) {
+        p2_batch_fwd<true>(f, t, mode, lds, s);
+    } else {
+        p2_batch_fwd<false>(f, t, mode, lds, s);
+    }
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const double *coef,
+                    double *values, double *rhs, unsigned flags, hipStream_t s)
+{
+    if (p->n_tiles == 0) return FEM_OK;
+    const int mode = scatter_mode(flags);
+    P2Args a = p2_args(p, m, f, coef);
+    a.load = rhs ? f->load : FEM_LOAD_NONE;
+    a.values = values;
+    a.rhs = rhs;
     a.use_first = mode != kAtomic && !(flags & FEM_ACCUMULATE);
     if (a.T > 64) return fail(FEM_ERR_UNSUPPORTED, "P2 tiles hold at most 64 elements");
-    const size_t lds = p2_lds_bytes(a.nmax, a.smax, a.T);
+    const size_t lds = p2_lds_bytes(a.nmax, a.smax, a.T, false);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "P2 tile needs more LDS than a CU has");
     const bool f32 = (flags & FEM_PREC_FP32) != 0;
     if (mode == kOrdered) {
@@ -523,10 +825,28 @@ int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
     return FEM_OK;
 }
 
-int p2_tile_backward(const fem_pattern *, const fem_mesh *, const fem_form *, const double *,
-                     const double *, const double *, double *, double *, unsigned, hipStream_t)
+int p2_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
+                     const double *coef, const double *gvalues, const double *grhs,
+                     double *gcoef, double *gcoords, unsigned flags, hipStream_t s)
 {
-    return fail(FEM_ERR_UNSUPPORTED, "elasticity adjoint not available in this build");
+    if (p->n_tiles == 0) return FEM_OK;
+    const int mode = scatter_mode(flags);
+    P2Args a = p2_args(p, m, f, coef);
+    a.load = grhs ? f->load : FEM_LOAD_NONE;
+    a.gvalues = gvalues;
+    a.grhs = grhs;
+    a.gcoef = gcoef;
+    a.gcoords = gcoords;
+    a.accumulate = (flags & FEM_ACCUMULATE) != 0;
+    a.use_first = mode != kAtomic && !a.accumulate;
+    if (a.T > 64) return fail(FEM_ERR_UNSUPPORTED, "P2 tiles hold at most 64 elements");
+    const size_t lds = p2_lds_bytes(a.nmax, a.smax, a.T, true);
+    if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "P2 tile needs more LDS than a CU has");
+    if (mode == kOrdered) p2_launch(k_p2_tile_bwd<kOrdered>, p, a, mode, lds, s);
+    else if (mode == kColoured) p2_launch(k_p2_tile_bwd<kColoured>, p, a, mode, lds, s);
+    else p2_launch(k_p2_tile_bwd<kAtomic>, p, a, mode, lds, s);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
 }
 
 }  // namespace fem

@@ -401,17 +401,29 @@ int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipS
         p->has_isolated_nodes = iso;
     }
     if (h_err & kErrSlotMissing) return fail(FEM_ERR_HIP, "internal: slot map lookup failed");
-    // default tile: 256 P1 elements (one per thread); 8 P2 elements (two per wavefront)
-    int tile = (p->order == 1) ? 256 : 8;
-    unsigned tsh = (flags >> 8) & 0xfu;
+    // Default tile, P1 (one element per thread): 192 tetrahedra -- in the locality order of
+    // a cube-like mesh of 6 tetrahedra per cell, an aligned 4x4x2-cell block, 26
+    // neighbour tiles -- or 256 triangles (an aligned 16x8-cell block).  P2: 8 elements
+    // (two per wavefront), in the input order (at that size the locality order saves no
+    // staging but gives the tile graph more neighbours, hence more colours).
+    int tile = (p->order == 2) ? 8 : (p->dim == 3 ? 192 : 256);
+    const unsigned tsh = (flags >> 8) & 0xfu, tw = (flags >> 12) & 0xfu;
     if (tsh) tile = 1 << tsh;
+    if (tw) tile = 64 * (int)tw;
     int rc = FEM_ERR_UNSUPPORTED;
     if (E > 0) {
-        rc = build_tile_plan(p, m->conn, tile, s);
+        LocalityOrder o;
+        if (!(flags & FEM_INPUT_ORDER) && p->order == 1) rc = build_locality_order(p, m, &o, s);
+        else rc = FEM_OK;
+        if (rc == FEM_OK)
+            rc = o.conn ? build_tile_plan(p, o.conn, o.slot, o.n2e, tile, s)
+                        : build_tile_plan(p, m->conn, p->slot, p->n2e, tile, s);
+        o.release(s);
         if (rc != FEM_OK && rc != FEM_ERR_UNSUPPORTED) return rc;
     }
     if (rc != FEM_OK) {
         clear_error();
+        p->telem = p->tpos = nullptr;  // the per-element path works in the input order
         FEM_TRY(build_element_colouring(p, m->conn, s));
     }
     return FEM_OK;

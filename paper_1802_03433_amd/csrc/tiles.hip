@@ -18,6 +18,8 @@
 // Intra-tile colours: greedy in element order, so LDS accumulation in colour phases is
 // deterministic.
 #include <algorithm>
+#include <set>
+#include <tuple>
 
 #include "fem_internal.h"
 
@@ -29,7 +31,7 @@ constexpr int kTT = 256;         // threads of the plan-building workgroups
 constexpr int kNodeCap = 2048;   // tile * npe candidates sorted in LDS
 constexpr int kMaxTilesPerNode = 32;
 
-enum : int { kErrPos = 1, kErrTilesPerNode = 2, kErrSub = 4, kErrMissing = 8, kErrColours = 16 };
+enum : int { kErrPos = 1, kErrTilesPerNode = 2, kErrSub = 4, kErrMissing = 8 };
 
 __device__ __forceinline__ int next_pow2(int c)
 {
@@ -88,16 +90,6 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int32_t 
         else hi = mid;
     }
     return lo;
-}
-
-__device__ __forceinline__ uint32_t prio_hash(uint32_t x)
-{
-    x ^= x >> 16;
-    x *= 0x7feb352du;
-    x ^= x >> 15;
-    x *= 0x846ca68bu;
-    x ^= x >> 16;
-    return x;
 }
 
 // Count (FILL = false) or list (FILL = true) each tile's distinct nodes; when listing,
@@ -218,70 +210,81 @@ __global__ void k_node_tiles(const int32_t *__restrict__ n2e_ptr, const int32_t 
     for (int q = 0; q < m; ++q) n2t[ptr[n] + q] = loc[q];
 }
 
-// One Jones-Plassmann round on the tile graph (tiles adjacent when they share a node).
-__global__ __launch_bounds__(kTT) void k_tile_colour_round(
-    const int32_t *__restrict__ cin, int32_t *__restrict__ cout, const int32_t *__restrict__ tnode_ptr,
-    const int32_t *__restrict__ tnode, const int32_t *__restrict__ n2t_ptr,
-    const int32_t *__restrict__ n2t, int *remaining, int *err)
+// Colouring of the tile graph (tiles adjacent when they share a node), on the host: the
+// graph is small (tiles x neighbours) and a sequential colouring needs far fewer colours
+// than a parallel one, which shortens the ordered scatter's dependency chains.  Two
+// deterministic orders are tried -- first fit in tile order, and DSATUR (most distinctly
+// coloured neighbours first, ties by degree then index) -- and the one with fewer colours
+// is kept (first fit on a tie).
+int colour_tile_graph(const std::vector<int32_t> &tptr, const std::vector<int32_t> &tn,
+                      const std::vector<int32_t> &nptr, const std::vector<int32_t> &nt2,
+                      int64_t nt, std::vector<int32_t> &colour)
 {
-    __shared__ int blocked;
-    __shared__ unsigned long long m0, m1;
-    const int32_t t = blockIdx.x;
-    const int32_t c = cin[t];
-    if (c >= 0) {
-        if (threadIdx.x == 0) cout[t] = c;
-        return;
-    }
-    if (threadIdx.x == 0) {
-        blocked = 0;
-        m0 = 0ull;
-        m1 = 0ull;
-    }
-    __syncthreads();
-    const uint32_t p = prio_hash((uint32_t)t);
-    unsigned long long l0 = 0, l1 = 0;
-    int bl = 0;
-    for (int32_t k = tnode_ptr[t] + threadIdx.x; k < tnode_ptr[t + 1]; k += kTT) {
-        int32_t n = tnode[k];
-        for (int32_t j = n2t_ptr[n]; j < n2t_ptr[n + 1]; ++j) {
-            int32_t t2 = n2t[j];
-            if (t2 == t) continue;
-            int32_t c2 = cin[t2];
-            if (c2 < 0) {
-                uint32_t p2 = prio_hash((uint32_t)t2);
-                if (p2 > p || (p2 == p && t2 > t)) bl = 1;
-            } else if (c2 < 64) {
-                l0 |= 1ull << c2;
-            } else {
-                l1 |= 1ull << (c2 - 64);
+    // neighbour lists, deduplicated with a marker
+    std::vector<int64_t> aptr((size_t)nt + 1, 0);
+    std::vector<int32_t> adj;
+    std::vector<int64_t> mark((size_t)nt, -1);
+    for (int64_t t = 0; t < nt; ++t) {
+        for (int32_t k = tptr[t]; k < tptr[t + 1]; ++k) {
+            const int32_t n = tn[k];
+            for (int32_t j = nptr[n]; j < nptr[n + 1]; ++j) {
+                const int32_t u = nt2[j];
+                if (u == t || mark[u] == t) continue;
+                mark[u] = t;
+                adj.push_back(u);
             }
         }
+        aptr[t + 1] = (int64_t)adj.size();
     }
-    if (bl) atomicOr(&blocked, 1);
-    if (l0) atomicOr(&m0, l0);
-    if (l1) atomicOr(&m1, l1);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (blocked) {
-            cout[t] = -1;
-            atomicAdd(remaining, 1);
-        } else {
-            int col;
-            if (~m0) col = __builtin_ctzll(~m0);
-            else if (~m1) col = 64 + __builtin_ctzll(~m1);
-            else {
-                atomicOr(err, kErrColours);
-                col = kMaxColours - 1;
+    auto first_fit = [&](const std::vector<int64_t> &order, std::vector<int32_t> &col) {
+        col.assign((size_t)nt, -1);
+        std::vector<int64_t> seen(kMaxColours + 1, -1);
+        int ncol = 0;
+        for (int64_t v : order) {
+            for (int64_t k = aptr[v]; k < aptr[v + 1]; ++k) {
+                const int32_t c = col[adj[k]];
+                if (c >= 0) seen[c] = v;
             }
-            cout[t] = col;
+            int c = 0;
+            while (c < kMaxColours && seen[c] == v) ++c;
+            col[v] = c;
+            ncol = std::max(ncol, c + 1);
+        }
+        return ncol;
+    };
+    std::vector<int64_t> order((size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) order[t] = t;
+    std::vector<int32_t> c1, c2;
+    const int n1 = first_fit(order, c1);
+    // DSATUR: saturation = number of distinct colours among coloured neighbours
+    c2.assign((size_t)nt, -1);
+    std::vector<std::vector<uint64_t>> satm((size_t)nt, std::vector<uint64_t>(kMaxColours / 64, 0ull));
+    std::vector<int32_t> sat((size_t)nt, 0);
+    using Key = std::tuple<int32_t, int64_t, int64_t>;  // (-saturation, -degree, index)
+    std::set<Key> q;
+    for (int64_t t = 0; t < nt; ++t) q.insert(Key(0, -(aptr[t + 1] - aptr[t]), t));
+    int n2 = 0;
+    while (!q.empty()) {
+        const int64_t v = std::get<2>(*q.begin());
+        q.erase(q.begin());
+        int c = 0;
+        while (c < kMaxColours && (satm[v][c >> 6] >> (c & 63) & 1ull)) ++c;
+        if (c >= kMaxColours) return fail(FEM_ERR_UNSUPPORTED, "tile colouring needs more than 128 colours");
+        c2[v] = c;
+        n2 = std::max(n2, c + 1);
+        for (int64_t k = aptr[v]; k < aptr[v + 1]; ++k) {
+            const int32_t u = adj[k];
+            if (c2[u] >= 0 || (satm[u][c >> 6] >> (c & 63) & 1ull)) continue;
+            q.erase(Key(-sat[u], -(aptr[u + 1] - aptr[u]), u));
+            satm[u][c >> 6] |= 1ull << (c & 63);
+            ++sat[u];
+            q.insert(Key(-sat[u], -(aptr[u + 1] - aptr[u]), u));
         }
     }
-}
-
-__global__ void k_fill_i32_t(int32_t *p, int64_t n, int32_t v)
-{
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) p[t] = v;
+    if (n1 >= kMaxColours && n2 >= kMaxColours)
+        return fail(FEM_ERR_UNSUPPORTED, "tile colouring needs more than 128 colours");
+    colour = (n2 < n1) ? c2 : c1;
+    return FEM_OK;
 }
 
 // For every tile node: which of the tile's slots (and the node's RHS entry) no tile of
@@ -317,6 +320,59 @@ __global__ __launch_bounds__(kTT) void k_tile_first(const int32_t *__restrict__ 
         }
         for (int w = 0; w < MW; ++w) tfirst[(int64_t)k * MW + w] = fb[w];
         trfirst[k] = rf;
+    }
+}
+
+// Distinct-slot list of every tile, precomputed so that the assembly kernels stage it with
+// one coalesced load: the tile nodes' row runs (mask bits in node order) concatenated.
+// P1 entries are node-level CSR slots, ~slot where the tile writes the slot first; P2
+// entries are codes (first << 31) | (tile node << 8) | row position.  tust[k] is the
+// offset of tile node k's run in its tile's list.
+template <bool FILL, int MW, bool PACKED>
+__global__ __launch_bounds__(kTT) void k_tile_slots(const int32_t *__restrict__ tnode_ptr,
+                                                    const int32_t *__restrict__ tnode,
+                                                    const uint64_t *__restrict__ trun,
+                                                    const uint64_t *__restrict__ tfirst,
+                                                    const int32_t *__restrict__ rowptr,
+                                                    int32_t *__restrict__ cnt,
+                                                    const int64_t *__restrict__ sptr,
+                                                    int32_t *__restrict__ tust,
+                                                    int32_t *__restrict__ tslot)
+{
+    __shared__ int scan_sh[kTT];
+    const int32_t t = blockIdx.x;
+    const int32_t n0 = tnode_ptr[t], nn = tnode_ptr[t + 1] - n0;
+    const int per = (nn + kTT - 1) / kTT;
+    const int k0 = min(nn, (int)threadIdx.x * per), k1 = min(nn, k0 + per);
+    int local = 0;
+    for (int k = k0; k < k1; ++k)
+        for (int w = 0; w < MW; ++w) local += __popcll(trun[(int64_t)(n0 + k) * MW + w]);
+    int total;
+    int off = block_scan_excl<kTT>(local, scan_sh, &total);
+    if (!FILL) {
+        if (threadIdx.x == 0) cnt[t] = total;
+        return;
+    }
+    int32_t *out = tslot + sptr[t];
+    for (int k = k0; k < k1; ++k) {
+        tust[n0 + k] = off;
+        const int32_t base = PACKED ? rowptr[tnode[n0 + k]] : 0;
+        for (int w = 0; w < MW; ++w) {
+            uint64_t r = trun[(int64_t)(n0 + k) * MW + w];
+            const uint64_t f = tfirst[(int64_t)(n0 + k) * MW + w];
+            while (r) {
+                const int b = __builtin_ctzll(r);
+                const bool first = (f >> b) & 1ull;
+                if (PACKED) {
+                    const int32_t slot = base + 64 * w + b;
+                    out[off] = first ? ~slot : slot;
+                } else {
+                    out[off] = (first ? (int32_t)0x80000000 : 0) | (k << 8) | (64 * w + b);
+                }
+                ++off;
+                r &= r - 1;
+            }
+        }
     }
 }
 
@@ -457,7 +513,8 @@ int scan_to_i32(TmpT &tmp, const int32_t *cnt, int64_t n, int32_t *out, int64_t 
 
 }  // namespace
 
-int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
+int build_tile_plan(fem_pattern *p, const int32_t *conn, const int32_t *slot, const int32_t *n2e,
+                    int T, hipStream_t s)
 {
     const int npe = p->npe;
     const int64_t E = p->n_elems, N = p->n_nodes;
@@ -468,7 +525,7 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
     const int node_row = p->max_row / p->ncomp;
     if (node_row > 64 * MW)
         return fail(FEM_ERR_UNSUPPORTED, "tile plan: row longer than the position masks");
-    if (packed && (T < 64 || T > 1024 || (T & (T - 1))))
+    if (packed && (T < 64 || T > 1024 || (T % 64) != 0))
         return fail(FEM_ERR_UNSUPPORTED, "tile plan: tile size out of range");
     if (T < 1 || T * npe > kNodeCap) return fail(FEM_ERR_UNSUPPORTED, "tile plan: tile too large");
     p->tile_mw = MW;
@@ -505,13 +562,13 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
         FEM_TRY(pattern_alloc(p, (void **)&p->enode, sizeof(uint64_t) * E));
         FEM_TRY(pattern_alloc(p, (void **)&p->epos, sizeof(uint32_t) * E * npe));
         hipLaunchKernelGGL((k_tile_nodes<true, 1, true>), dim3((unsigned)nt), dim3(kTT), 0, s, conn,
-                           E, npe, T, nullptr, p->tnode_ptr, p->tnode, (void *)p->enode, p->slot,
+                           E, npe, T, nullptr, p->tnode_ptr, p->tnode, (void *)p->enode, slot,
                            p->rowptr_n, (void *)p->epos, p->trun, d_max, d_err);
     } else {
         FEM_TRY(pattern_alloc(p, (void **)&p->enode16, sizeof(uint16_t) * E * npe));
         FEM_TRY(pattern_alloc(p, (void **)&p->epos8, sizeof(uint8_t) * E * npe * npe));
         hipLaunchKernelGGL((k_tile_nodes<true, 2, false>), dim3((unsigned)nt), dim3(kTT), 0, s, conn,
-                           E, npe, T, nullptr, p->tnode_ptr, p->tnode, (void *)p->enode16, p->slot,
+                           E, npe, T, nullptr, p->tnode_ptr, p->tnode, (void *)p->enode16, slot,
                            p->rowptr_n, (void *)p->epos8, p->trun, d_max, d_err);
     }
 
@@ -520,12 +577,12 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
     FEM_TRY(tmp.get(&n2t_cnt, N));
     FEM_TRY(tmp.get(&n2t_ptr, N + 1));
     hipLaunchKernelGGL((k_node_tiles<false>), dim3(grid_for(N, kTT)), dim3(kTT), 0, s, p->n2e_ptr,
-                       p->n2e, N, T, n2t_cnt, nullptr, nullptr, d_err);
+                       n2e, N, T, n2t_cnt, nullptr, nullptr, d_err);
     int64_t n_n2t = 0;
     FEM_TRY(scan_to_i32(tmp, n2t_cnt, N, n2t_ptr, &n_n2t, s));
     FEM_TRY(tmp.get(&n2t, n_n2t));
     hipLaunchKernelGGL((k_node_tiles<true>), dim3(grid_for(N, kTT)), dim3(kTT), 0, s, p->n2e_ptr,
-                       p->n2e, N, T, nullptr, n2t_ptr, n2t, d_err);
+                       n2e, N, T, nullptr, n2t_ptr, n2t, d_err);
     int h_err = 0, h_max[2] = {0, 0};
     FEM_HIP_TRY(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
     FEM_HIP_TRY(hipMemcpyAsync(h_max, d_max, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -536,30 +593,25 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
     p->tile_max_nodes = h_max[0];
     p->tile_max_slots = h_max[1];
 
-    // tile colouring
+    // tile colouring (host)
     FEM_TRY(pattern_alloc(p, (void **)&p->tile_colour, sizeof(int32_t) * nt));
-    int32_t *cA = nullptr;
-    FEM_TRY(tmp.get(&cA, nt));
-    hipLaunchKernelGGL(k_fill_i32_t, dim3(grid_for(nt, kTT)), dim3(kTT), 0, s, cA, nt, (int32_t)-1);
-    constexpr int kRounds = 4;
-    int *d_rem = nullptr;
-    FEM_TRY(tmp.get(&d_rem, kRounds));
-    int32_t *cur = cA, *nxt = p->tile_colour;
-    for (int rounds = 0;; rounds += kRounds) {
-        FEM_HIP_TRY(hipMemsetAsync(d_rem, 0, sizeof(int) * kRounds, s));
-        for (int r = 0; r < kRounds; ++r) {
-            hipLaunchKernelGGL(k_tile_colour_round, dim3((unsigned)nt), dim3(kTT), 0, s, cur, nxt,
-                               p->tnode_ptr, p->tnode, n2t_ptr, n2t, d_rem + r, d_err);
-            std::swap(cur, nxt);
-        }
-        bool done = false;
-        FEM_TRY(jp_rounds_check(d_rem, kRounds, d_err, s, &done));
-        if (done) break;
-        if (rounds > 100000) return fail(FEM_ERR_HIP, "tile colouring did not terminate");
+    {
+        std::vector<int32_t> h_tptr((size_t)nt + 1), h_tn((size_t)n_tn), h_nptr((size_t)N + 1),
+            h_n2t((size_t)n_n2t), col;
+        FEM_HIP_TRY(hipMemcpyAsync(h_tptr.data(), p->tnode_ptr, sizeof(int32_t) * (nt + 1),
+                                   hipMemcpyDeviceToHost, s));
+        FEM_HIP_TRY(hipMemcpyAsync(h_tn.data(), p->tnode, sizeof(int32_t) * n_tn,
+                                   hipMemcpyDeviceToHost, s));
+        FEM_HIP_TRY(hipMemcpyAsync(h_nptr.data(), n2t_ptr, sizeof(int32_t) * (N + 1),
+                                   hipMemcpyDeviceToHost, s));
+        FEM_HIP_TRY(hipMemcpyAsync(h_n2t.data(), n2t, sizeof(int32_t) * n_n2t,
+                                   hipMemcpyDeviceToHost, s));
+        FEM_HIP_TRY(hipStreamSynchronize(s));
+        FEM_TRY(colour_tile_graph(h_tptr, h_tn, h_nptr, h_n2t, nt, col));
+        FEM_HIP_TRY(hipMemcpyAsync(p->tile_colour, col.data(), sizeof(int32_t) * nt,
+                                   hipMemcpyHostToDevice, s));
+        FEM_HIP_TRY(hipStreamSynchronize(s));
     }
-    if (cur != p->tile_colour)
-        FEM_HIP_TRY(hipMemcpyAsync(p->tile_colour, cur, sizeof(int32_t) * nt,
-                                   hipMemcpyDeviceToDevice, s));
     FEM_TRY(pattern_alloc(p, (void **)&p->tile_perm, sizeof(int32_t) * nt));
     FEM_TRY(sort_by_colour(p->tile_colour, nt, p->tile_perm, p->tile_colour_ptr, s));
     p->n_tile_colours = (int32_t)p->tile_colour_ptr.size() - 1;
@@ -571,6 +623,35 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, int T, hipStream_t s)
     else
         hipLaunchKernelGGL(k_tile_first<2>, dim3((unsigned)nt), dim3(kTT), 0, s, p->tile_colour,
                            p->tnode_ptr, p->tnode, p->trun, n2t_ptr, n2t, p->tfirst, p->trfirst, d_err);
+    // distinct-slot lists (after the first-writer masks)
+    {
+        int32_t *scnt = nullptr;
+        int64_t *sptr64 = nullptr;
+        FEM_TRY(tmp.get(&scnt, nt));
+        FEM_TRY(pattern_alloc(p, (void **)&p->tslot_ptr, sizeof(int64_t) * (nt + 1)));
+        FEM_TRY(pattern_alloc(p, (void **)&p->tust, sizeof(int32_t) * n_tn));
+        if (packed)
+            hipLaunchKernelGGL((k_tile_slots<false, 1, true>), dim3((unsigned)nt), dim3(kTT), 0, s,
+                               p->tnode_ptr, p->tnode, p->trun, p->tfirst, p->rowptr_n, scnt,
+                               nullptr, nullptr, nullptr);
+        else
+            hipLaunchKernelGGL((k_tile_slots<false, 2, false>), dim3((unsigned)nt), dim3(kTT), 0, s,
+                               p->tnode_ptr, p->tnode, p->trun, p->tfirst, p->rowptr_n, scnt,
+                               nullptr, nullptr, nullptr);
+        FEM_TRY(scan_counts_i64(scnt, p->tslot_ptr, nt, s));
+        int64_t n_slots = 0;
+        FEM_HIP_TRY(hipMemcpyAsync(&n_slots, p->tslot_ptr + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        FEM_HIP_TRY(hipStreamSynchronize(s));
+        FEM_TRY(pattern_alloc(p, (void **)&p->tslot, sizeof(int32_t) * n_slots));
+        if (packed)
+            hipLaunchKernelGGL((k_tile_slots<true, 1, true>), dim3((unsigned)nt), dim3(kTT), 0, s,
+                               p->tnode_ptr, p->tnode, p->trun, p->tfirst, p->rowptr_n, nullptr,
+                               p->tslot_ptr, p->tust, p->tslot);
+        else
+            hipLaunchKernelGGL((k_tile_slots<true, 2, false>), dim3((unsigned)nt), dim3(kTT), 0, s,
+                               p->tnode_ptr, p->tnode, p->trun, p->tfirst, p->rowptr_n, nullptr,
+                               p->tslot_ptr, p->tust, p->tslot);
+    }
     FEM_TRY(pattern_alloc(p, (void **)&p->esub, sizeof(uint8_t) * E));
     FEM_TRY(pattern_alloc(p, (void **)&p->tile_nsub, sizeof(int32_t) * nt));
     if (packed)

@@ -1,0 +1,246 @@
+"""GPU tests of batched assembly (many meshes, one block-diagonal system, one launch per
+element family): the block-diagonal CSR against the oracle's per-mesh patterns with
+offsets; every mesh's block against its own single-mesh assembly (bit-identical in the
+coloured modes) and against the oracle (the 1e-12 scaled rule); the adjoint likewise;
+graph capture of a batched call; the mixed 512-mesh batch at full size on sampled meshes."""
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+from tests._util import scaled_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+BF = (0.0, 0.0, -1.0)
+
+
+def fem():
+    import paper_1802_03433_amd as F
+
+    return F
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _member(n, order, dim, seed):
+    if dim == 2:
+        m = meshgen.square_tri(n, seed=seed)
+        return m, "helmholtz"
+    m = meshgen.cube_tet(n, order, seed=seed)
+    return m, ("elasticity" if order == 2 else "helmholtz")
+
+
+def _form(F, kind, dim):
+    if kind == "elasticity":
+        return F.Form("elasticity", "const", load_const=BF)
+    return F.Form("helmholtz", "sinprod", reaction=1.0)
+
+
+# a small mixed batch: P1 tetrahedra, P2 tetrahedra and P1 triangles, interleaved
+SMALL = [(3, 1, 3), (2, 2, 3), (5, 1, 2), (1, 2, 3), (4, 1, 3), (3, 2, 3), (1, 1, 3),
+         (7, 1, 2), (2, 1, 3), (2, 2, 3)]
+
+
+def _small_batch(seed=0):
+    F = fem()
+    dev = torch.device("cuda:0")
+    hm, dm, forms, coefs = [], [], [], []
+    for k, (n, order, dim) in enumerate(SMALL):
+        m, kind = _member(n, order, dim, seed + 17 * k)
+        hm.append(m)
+        dm.append(F.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev), order))
+        forms.append(_form(F, kind, dim))
+        coefs.append(torch.from_numpy(meshgen.coefficients(m.n_elems, kind, seed=seed + k)).to(dev))
+    return F, hm, dm, forms, coefs
+
+
+def _oracle_forward(m, form, coef):
+    if form.kind == "elasticity":
+        rp, ci = oracle.pattern(10, 3, m.n_nodes, m.conn)
+        return (rp, ci) + oracle.assemble_p2_elasticity(m, coef[0], coef[1], "const", BF, rp, ci)
+    rp, ci = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+    return (rp, ci) + oracle.assemble_p1(m, coef[0], 1.0, "sinprod", None, rp, ci)
+
+
+def test_batch_offsets_and_export():
+    F, hm, dm, forms, coefs = _small_batch()
+    b = F.Batch(dm)
+    assert b.n_meshes == len(SMALL) and b.n_families == 3
+    rp, ci = (_np(t) for t in b.export())
+    assert rp[0] == 0 and rp[-1] == b.nnz
+    for k, m in enumerate(hm):
+        ncomp = 3 if m.order == 2 else 1
+        orp, oci = oracle.pattern(m.npe, ncomp, m.n_nodes, m.conn)
+        r0, r1 = b.row_offset[k], b.row_offset[k + 1]
+        z0, z1 = b.nnz_offset[k], b.nnz_offset[k + 1]
+        assert r1 - r0 == m.n_nodes * ncomp and z1 - z0 == int(orp[-1])
+        np.testing.assert_array_equal(rp[r0:r1 + 1] - z0, orp)
+        np.testing.assert_array_equal(ci[z0:z1] - r0, oci)
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "coloured", "coloured-launches"])
+def test_batch_forward(scatter):
+    F, hm, dm, forms, coefs = _small_batch(1)
+    b = F.Batch(dm)
+    v, r = F.assemble_batch(b, dm, forms, coefs, scatter=scatter)
+    v, r = _np(v), _np(r)
+    for k, m in enumerate(hm):
+        ncomp = 3 if m.order == 2 else 1
+        pat = F.Pattern(dm[k], ncomp=ncomp)
+        sv, sr = F.assemble(pat, dm[k], forms[k], coefs[k], scatter=scatter)
+        bv, br = b.block(torch.from_numpy(v), k).numpy(), b.block(torch.from_numpy(r), k, rows=True).numpy()
+        if scatter != "atomic":
+            assert bv.tobytes() == _np(sv).tobytes(), k
+            assert br.tobytes() == _np(sr).tobytes(), k
+        _, _, ov, orhs, oav, oar = _oracle_forward(m, forms[k], coefs[k].cpu().numpy())
+        ok, worst = scaled_close(bv, ov, oav, RTOL)
+        assert ok, (k, worst)
+        ok, worst = scaled_close(br, orhs, oar, RTOL)
+        assert ok, (k, worst)
+
+
+def test_batch_ordered_equals_launches_and_is_reproducible():
+    F, hm, dm, forms, coefs = _small_batch(2)
+    b = F.Batch(dm)
+    outs = []
+    for sc in ("coloured", "coloured-launches", "coloured"):
+        v, r = F.assemble_batch(b, dm, forms, coefs, scatter=sc)
+        outs.append((_np(v).tobytes(), _np(r).tobytes()))
+    assert outs[0] == outs[1] == outs[2]
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "coloured"])
+def test_batch_backward(scatter):
+    F, hm, dm, forms, coefs = _small_batch(3)
+    dev = torch.device("cuda:0")
+    b = F.Batch(dm)
+    G, g = (torch.from_numpy(a).to(dev) for a in meshgen.upstream_grads(b.nnz, b.n_rows, seed=3))
+    gcs, gxs = F.assemble_backward_batch(b, dm, forms, coefs, G, g, scatter=scatter)
+    for k, m in enumerate(hm):
+        ncomp = 3 if m.order == 2 else 1
+        Gk, gk = b.block(G, k).contiguous(), b.block(g, k, rows=True).contiguous()
+        pat = F.Pattern(dm[k], ncomp=ncomp)
+        sc_, sx = F.assemble_backward(pat, dm[k], forms[k], coefs[k], Gk, gk, scatter=scatter)
+        if scatter != "atomic":
+            assert _np(gcs[k]).tobytes() == _np(sc_).tobytes(), k
+            assert _np(gxs[k]).tobytes() == _np(sx).tobytes(), k
+        c = coefs[k].cpu().numpy()
+        Gn, gn = Gk.cpu().numpy(), gk.cpu().numpy()
+        if forms[k].kind == "elasticity":
+            rp, ci = oracle.pattern(10, 3, m.n_nodes, m.conn)
+            dl, adl, dmu, admu, dx, adx = oracle.backward_p2_elasticity(m, c[0], c[1], "const", BF,
+                                                                        rp, ci, Gn, gn)
+            assert scaled_close(_np(gcs[k])[0], dl, adl, RTOL)[0], k
+            assert scaled_close(_np(gcs[k])[1], dmu, admu, RTOL)[0], k
+        else:
+            rp, ci = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+            dk, adk, dx, adx = oracle.backward_p1(m, c[0], 1.0, "sinprod", None, rp, ci, Gn, gn)
+            assert scaled_close(_np(gcs[k])[0], dk, adk, RTOL)[0], k
+        ok, worst = scaled_close(_np(gxs[k]), dx, adx, RTOL)
+        assert ok, (k, worst)
+
+
+def test_batch_graph_capture_replays():
+    """A batched forward + adjoint captured into one HIP graph, replayed several times
+    with eager work and synchronisations between replays; every replay reproduces the
+    eager result bit for bit (coloured scatter)."""
+    F, hm, dm, forms, coefs = _small_batch(4)
+    dev = torch.device("cuda:0")
+    b = F.Batch(dm)
+    G, g = (torch.from_numpy(a).to(dev) for a in meshgen.upstream_grads(b.nnz, b.n_rows, seed=4))
+    values = torch.empty(b.nnz, dtype=torch.float64, device=dev)
+    rhs = torch.empty(b.n_rows, dtype=torch.float64, device=dev)
+    gcs = [torch.empty_like(c) for c in coefs]
+    gxs = [torch.empty_like(m.coords) for m in dm]
+
+    def step():
+        F.assemble_batch(b, dm, forms, coefs, values, rhs, scatter="coloured")
+        F.assemble_backward_batch(b, dm, forms, coefs, G, g, scatter="coloured",
+                                  grad_coef=gcs, grad_coords=gxs)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()  # uploads the argument tables outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    ref = [_np(values).copy(), _np(rhs).copy()] + [_np(t).copy() for t in gcs + gxs]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        values.fill_(float("nan"))
+        rhs.fill_(float("nan"))
+        for t in gcs + gxs:
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [_np(values), _np(rhs)] + [_np(t) for t in gcs + gxs]
+        for a, c in zip(ref, got):
+            assert a.tobytes() == c.tobytes(), rep
+        _ = (values * 2).sum().item()  # eager work between replays
+
+
+def test_batch_rejects_mixed_loads_in_a_family():
+    F, hm, dm, forms, coefs = _small_batch(5)
+    b = F.Batch(dm)
+    bad = list(forms)
+    first_p1 = next(k for k, m in enumerate(hm) if m.order == 1 and m.dim == 3)
+    bad[first_p1] = F.Form("helmholtz", "const", load_const=(1.0,))
+    with pytest.raises(F.FemError) as ei:
+        F.assemble_batch(b, dm, bad, coefs, scatter="coloured")
+    assert ei.value.code == -2
+
+
+def _c4_plan():
+    return meshgen.batch_plan(512, 6, 32, seed=0)
+
+
+def test_batch_full_size_sampled():
+    """The 512-mesh mixed batch (n ~ U{6..32}, half P1 Helmholtz, half P2 elasticity):
+    block-diagonal sizes against the closed forms, int64 offsets past 2^31 - 1 stored
+    entries, and sampled meshes' blocks bit-identical to their single-mesh assembly
+    (coloured) plus two small sampled meshes against the oracle."""
+    F = fem()
+    dev = torch.device("cuda:0")
+    plan = _c4_plan()
+    hm, dm, forms, coefs = [], [], [], []
+    for n, order, kind, seed in plan:
+        m = meshgen.cube_tet(n, order, seed=seed)
+        hm.append(m)
+        dm.append(F.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev), order))
+        forms.append(_form(F, kind, 3))
+        coefs.append(torch.from_numpy(meshgen.coefficients(m.n_elems, kind, seed=seed)).to(dev))
+    b = F.Batch(dm)
+    # closed forms: scalar P1 nnz 15n^3+21n^2+9n+1, P2 vector nnz 9 (230n^3+138n^2+24n+1)
+    exp = sum(15 * n ** 3 + 21 * n ** 2 + 9 * n + 1 if o == 1 else
+              9 * (230 * n ** 3 + 138 * n ** 2 + 24 * n + 1) for n, o, _, _ in plan)
+    assert b.nnz == exp and b.nnz > 2 ** 31 - 1
+    print(f"batch: {b.n_meshes} meshes, {sum(m.n_elems for m in hm)} elements, "
+          f"{b.n_rows} rows, {b.nnz} stored entries, {b.n_tiles} tiles", flush=True)
+    values = torch.empty(b.nnz, dtype=torch.float64, device=dev)
+    rhs = torch.empty(b.n_rows, dtype=torch.float64, device=dev)
+    F.assemble_batch(b, dm, forms, coefs, values, rhs, scatter="coloured")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    sample = list(rng.choice(len(plan), 6, replace=False)) + [len(plan) - 1]
+    for k in sample:
+        pat = F.Pattern(dm[k], ncomp=3 if hm[k].order == 2 else 1)
+        sv, sr = F.assemble(pat, dm[k], forms[k], coefs[k], scatter="coloured")
+        assert _np(b.block(values, k)).tobytes() == _np(sv).tobytes(), k
+        assert _np(b.block(rhs, k, rows=True)).tobytes() == _np(sr).tobytes(), k
+        pat.close()
+    # oracle on the smallest P1 and P2 members
+    for order in (1, 2):
+        k = min((k for k in range(len(plan)) if plan[k][1] == order), key=lambda k: plan[k][0])
+        _, _, ov, orhs, oav, oar = _oracle_forward(hm[k], forms[k], coefs[k].cpu().numpy())
+        assert scaled_close(_np(b.block(values, k)), ov, oav, RTOL)[0], k
+        assert scaled_close(_np(b.block(rhs, k, rows=True)), orhs, oar, RTOL)[0], k

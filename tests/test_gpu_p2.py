@@ -169,3 +169,179 @@ def test_p2_fp32_matrix_cores_error():
     assert 0 < rel < 1e-5
     # the load is not a contraction: same FP64 arithmetic, up to the atomic summation order
     np.testing.assert_allclose(_np(r32), _np(r64), rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------------------
+# adjoint: dL/dlam, dL/dmu (per element) and dL/dx (vertex nodes) for
+# L = <grad_values, values> + <grad_rhs, rhs>
+# ---------------------------------------------------------------------------------------
+def _bwd_case(n, seed):
+    m = meshgen.cube_tet(n, 2, seed=seed)
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d, ncomp=3)
+    coef = meshgen.coefficients(m.n_elems, "elasticity", seed=seed)
+    G, g = meshgen.upstream_grads(pat.nnz, pat.n_rows, seed=seed)
+    return m, F, d, pat, coef, G, g
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "coloured"])
+@pytest.mark.parametrize("load", ["none", "const"])
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_p2_backward_parity(n, load, scatter):
+    m, F, d, pat, coef, G, g = _bwd_case(n, 40 + n)
+    form = F.Form("elasticity", load, load_const=BF)
+    gc, gx = F.assemble_backward(pat, d, form, torch.from_numpy(coef).cuda(),
+                                 torch.from_numpy(G).cuda(), torch.from_numpy(g).cuda(),
+                                 scatter=scatter)
+    rp, ci = oracle.pattern(10, 3, m.n_nodes, m.conn)
+    dl, adl, dm, adm, dx, adx = oracle.backward_p2_elasticity(m, coef[0], coef[1], load, BF,
+                                                              rp, ci, G, g)
+    gc, gx = _np(gc), _np(gx)
+    ok, worst = scaled_close(gc[0], dl, adl, RTOL)
+    assert ok, worst
+    ok, worst = scaled_close(gc[1], dm, adm, RTOL)
+    assert ok, worst
+    ok, worst = scaled_close(gx, dx, adx, RTOL)
+    assert ok, worst
+    # edge nodes receive exactly zero
+    edge = np.setdiff1d(np.arange(m.n_nodes), np.unique(m.conn[:4]))
+    assert np.all(gx[:, edge] == 0.0)
+
+
+def test_p2_backward_partial_requests():
+    """grad_values only / grad_rhs only / coefficient or coordinate gradient alone give
+    the same numbers as the full call restricted accordingly."""
+    m, F, d, pat, coef, G, g = _bwd_case(3, 51)
+    form = F.Form("elasticity", "const", load_const=BF)
+    c, Gt, gt = (torch.from_numpy(a).cuda() for a in (coef, G, g))
+    rp, ci = oracle.pattern(10, 3, m.n_nodes, m.conn)
+    for Gi, gi in ((Gt, None), (None, gt)):
+        gc, gx = F.assemble_backward(pat, d, form, c, Gi, gi, scatter="coloured")
+        dl, adl, dm, adm, dx, adx = oracle.backward_p2_elasticity(
+            m, coef[0], coef[1], "const", BF, rp, ci,
+            None if Gi is None else G, None if gi is None else g)
+        assert scaled_close(_np(gc)[0], dl, adl, RTOL)[0]
+        assert scaled_close(_np(gc)[1], dm, adm, RTOL)[0]
+        assert scaled_close(_np(gx), dx, adx, RTOL)[0]
+    gc_full, gx_full = F.assemble_backward(pat, d, form, c, Gt, gt, scatter="coloured")
+    gc_only, none_x = F.assemble_backward(pat, d, form, c, Gt, gt, want_coords=False,
+                                          scatter="coloured")
+    none_c, gx_only = F.assemble_backward(pat, d, form, c, Gt, gt, want_coef=False,
+                                          scatter="coloured")
+    assert none_x is None and none_c is None
+    assert _np(gc_only).tobytes() == _np(gc_full).tobytes()
+    assert _np(gx_only).tobytes() == _np(gx_full).tobytes()
+
+
+def test_p2_backward_ordered_equals_colour_launches():
+    m, F, d, pat, coef, G, g = _bwd_case(5, 52)
+    form = F.Form("elasticity", "const", load_const=BF)
+    c, Gt, gt = (torch.from_numpy(a).cuda() for a in (coef, G, g))
+    outs = {}
+    for sc in ("coloured", "coloured-launches", "coloured"):
+        gc, gx = F.assemble_backward(pat, d, form, c, Gt, gt, scatter=sc)
+        outs.setdefault(sc, []).append((_np(gc).tobytes(), _np(gx).tobytes()))
+    assert outs["coloured"][0] == outs["coloured"][1]
+    assert outs["coloured"][0] == outs["coloured-launches"][0]
+
+
+def test_p2_backward_accumulate():
+    m, F, d, pat, coef, G, g = _bwd_case(2, 53)
+    form = F.Form("elasticity", "const", load_const=BF)
+    c, Gt, gt = (torch.from_numpy(a).cuda() for a in (coef, G, g))
+    for sc in ("atomic", "coloured"):
+        gc, gx = F.assemble_backward(pat, d, form, c, Gt, gt, scatter=sc)
+        gc0, gx0 = _np(gc).copy(), _np(gx).copy()
+        rng = np.random.default_rng(3)
+        X, Y = rng.standard_normal(gc0.shape), rng.standard_normal(gx0.shape)
+        gc.copy_(torch.from_numpy(X))
+        gx.copy_(torch.from_numpy(Y))
+        F.assemble_backward(pat, d, form, c, Gt, gt, scatter=sc, accumulate=True,
+                            grad_coef=gc, grad_coords=gx)
+        np.testing.assert_allclose(_np(gc), X + gc0, rtol=1e-13, atol=1e-13 * np.abs(gc0).max())
+        np.testing.assert_allclose(_np(gx), Y + gx0, rtol=1e-13, atol=1e-13 * np.abs(gx0).max())
+
+
+def test_p2_fd_and_invariants():
+    """Central differences of the GPU forward against the GPU adjoint: L is affine in
+    lam and mu (exact differences); step 1e-6 on vertex coordinates.  Properties that
+    hold at any size: translation invariance of dL/dx, and Euler homogeneity
+    sum_n x_n . dL/dx_n = L_K + 3 L_b (the stiffness scales as h, the load as h^3)."""
+    m, F, d, pat, coef, G, g = _bwd_case(4, 54)
+    dev = torch.device("cuda:0")
+    form = F.Form("elasticity", "const", load_const=BF)
+    c, Gt, gt = (torch.from_numpy(a).to(dev) for a in (coef, G, g))
+    gc, gx = F.assemble_backward(pat, d, form, c, Gt, gt, scatter="coloured")
+    gc, gx = _np(gc), _np(gx)
+
+    def L_diff(mp, cp, mm, cm):
+        vp, rp_ = F.assemble(pat, mp, form, cp, scatter="coloured")
+        vm, rm = F.assemble(pat, mm, form, cm, scatter="coloured")
+        return float(((vp - vm) * Gt).sum() + ((rp_ - rm) * gt).sum())
+
+    rng = np.random.default_rng(11)
+    for e in rng.choice(m.n_elems, 16, replace=False):
+        for k in range(2):
+            cp, cm = c.clone(), c.clone()
+            cp[k, e] += 0.5
+            cm[k, e] -= 0.5
+            fd = L_diff(d, cp, d, cm)
+            assert abs(fd - gc[k, e]) <= 1e-10 * max(abs(gc[k, e]), np.abs(gc[k]).max()), (k, e)
+    h = 1e-6
+    verts = np.unique(m.conn[:4])
+    for n in rng.choice(verts, 24, replace=False):
+        a = int(rng.integers(0, 3))
+        cp, cm = d.coords.clone(), d.coords.clone()
+        cp[a, n] += h
+        cm[a, n] -= h
+        fd = L_diff(d.with_coords(cp), c, d.with_coords(cm), c) / (2 * h)
+        assert abs(fd - gx[a, n]) <= 1e-6 * max(abs(gx[a, n]), 1e-3 * np.abs(gx).max()), (n, a)
+    # invariants
+    assert np.abs(gx.sum(1)).max() <= 1e-12 * np.abs(gx).max() * m.n_nodes ** 0.5
+    v, r = F.assemble(pat, d, form, c, scatter="coloured")
+    LK, Lb = float((v * Gt).sum()), float((r * gt).sum())
+    euler = float(np.sum(m.coords * gx))
+    assert euler == pytest.approx(LK + 3 * Lb, rel=1e-11, abs=1e-11 * (abs(LK) + abs(Lb)))
+
+
+def test_p2_autograd_function():
+    m, F, d, pat, coef, G, g = _bwd_case(3, 55)
+    form = F.Form("elasticity", "const", load_const=BF)
+    c, Gt, gt = (torch.from_numpy(a).cuda() for a in (coef, G, g))
+    coords = d.coords.clone().requires_grad_(True)
+    cc = c.clone().requires_grad_(True)
+    v, r = F.fem_assemble(coords, cc, pat, d, form, scatter="coloured")
+    ((v * Gt).sum() + (r * gt).sum()).backward()
+    gc, gx = F.assemble_backward(pat, d, form, c, Gt, gt, scatter="coloured")
+    assert _np(cc.grad).tobytes() == _np(gc).tobytes()
+    assert _np(coords.grad).tobytes() == _np(gx).tobytes()
+
+
+def test_p2_backward_full_size_sampled():
+    """40^3 x 6 P2 mesh in the benchmark's launch configuration; the oracle evaluates
+    64 sampled elements' dL/dlam, dL/dmu and 16 sampled vertex nodes' dL/dx (on the
+    sub-mesh of the elements around them, which is exact for those nodes)."""
+    m, coef, rp, ci, _ = c2()
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d, ncomp=3)
+    G, g = meshgen.upstream_grads(pat.nnz, pat.n_rows, seed=56)
+    form = F.Form("elasticity", "const", load_const=BF)
+    gc, gx = F.assemble_backward(pat, d, form, torch.from_numpy(coef).cuda(),
+                                 torch.from_numpy(G).cuda(), torch.from_numpy(g).cuda())
+    gc, gx = _np(gc), _np(gx)
+    rng = np.random.default_rng(56)
+    els = np.sort(rng.choice(m.n_elems, 64, replace=False))
+    sub = meshgen.Mesh(3, 2, m.n, m.coords, np.ascontiguousarray(m.conn[:, els]))
+    dl, adl, dm, adm, _, _ = oracle.backward_p2_elasticity(
+        sub, coef[0, els], coef[1, els], "const", BF, rp, ci, G, g, want_coords=False)
+    assert scaled_close(gc[0, els], dl, adl, RTOL)[0]
+    assert scaled_close(gc[1, els], dm, adm, RTOL)[0]
+    nodes = rng.choice(np.unique(m.conn[:4]), 16, replace=False)
+    around = np.nonzero(np.isin(m.conn[:4], nodes).any(0))[0]
+    sub = meshgen.Mesh(3, 2, m.n, m.coords, np.ascontiguousarray(m.conn[:, around]))
+    _, _, _, _, dx, adx = oracle.backward_p2_elasticity(
+        sub, coef[0, around], coef[1, around], "const", BF, rp, ci, G, g)
+    ok, worst = scaled_close(gx[:, nodes], dx[:, nodes], adx[:, nodes], RTOL)
+    assert ok, worst
