@@ -17,6 +17,7 @@ graph-captured).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N_CELLS = 64
+# HBM traffic of the P1 forward kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
+# valid while the kernel's sources are the ones the counters were taken on
+HBM_PROFILE = os.path.join(ROOT, "profiles", "p1_tile_fwd_cube64_hbm.txt")
+KERNEL_SOURCES = ("paper_1802_03433_amd/csrc/p1_tile.hip", "paper_1802_03433_amd/csrc/fem_internal.h",
+                  "paper_1802_03433_amd/csrc/quadrature.h", "paper_1802_03433_amd/csrc/tiles.hip",
+                  "paper_1802_03433_amd/csrc/order.hip", "paper_1802_03433_amd/csrc/pattern.hip",
+                  "paper_1802_03433_amd/build.py")
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _measured_traffic():
+    """Bytes per launch from the committed counter summary, or None if it is missing or
+    was taken on other kernel sources."""
+    try:
+        fields = {}
+        with open(HBM_PROFILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        if fields.get("sources_sha256") != kernel_sources_hash():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _alg_bytes_fwd(E, N, nnz, npe=4, with_rhs=True):
@@ -236,7 +269,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--sections", default="p1,p2,batch",
+                    help="extra legs to run: comma list of p1 (P1 variants and adjoint), p2, batch")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 512 MiB copy three times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": x.numel() * 8, "bytes_written": y.numel() * 8}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -306,15 +353,18 @@ def main():
             "peak": 8000.0,
             "unit": "GB/s",
             "frac": achieved / 8000.0,
-            "traffic": None,
+            "traffic": _measured_traffic(),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "k_p1_tile_fwd<3,sinprod,%s>" % ("atomic" if args.scatter == "atomic" else "ordered"),
             "kernel_us": kernel_ms * 1e3,
             "alg_bytes": alg,
         },
     }
 
+    sections = set(args.sections.split(","))
     if not args.no_extra:
         extra = {"pattern_build_ms": pattern_ms, "n_colours": pat.n_colours}
+    if not args.no_extra and "p1" in sections:
         other = "coloured" if args.scatter == "atomic" else "atomic"
 
         def step_other():
@@ -342,11 +392,13 @@ def main():
         extra["bwd_ms"] = bwd_ms
         extra["bwd_over_fwd"] = bwd_ms / ms_per_step
         extra["bwd_alg_GBps"] = _alg_bytes_bwd(E, N, nnz) / (bwd_ms * 1e-3) / 1e9
+    if not args.no_extra and "p2" in sections:
         extra["p2_elasticity"] = _bench_p2(torch, fem, meshgen, dev, max(5, args.steps // 3))
         torch.cuda.empty_cache()
-        if not args.no_batch:
-            extra["batch_512"] = _bench_batch(torch, fem, meshgen, dev, args.steps)
-            torch.cuda.empty_cache()
+    if not args.no_extra and "batch" in sections and not args.no_batch:
+        extra["batch_512"] = _bench_batch(torch, fem, meshgen, dev, args.steps)
+        torch.cuda.empty_cache()
+    if not args.no_extra:
         out["extra"] = extra
 
     if not args.no_cpu_baseline:
