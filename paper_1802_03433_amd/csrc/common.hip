@@ -1,4 +1,7 @@
 // Error state, device scans and fills shared by the library's kernels.
+#include <map>
+#include <mutex>
+
 #include "fem_internal.h"
 
 namespace fem {
@@ -8,6 +11,20 @@ static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 const char *last_error() { return g_last_error.c_str(); }
+
+void ensure_lds_attr(const void *kernel, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, size_t> done;  // (device, kernel) -> bytes
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &d = done[{dev, kernel}];
+    if (lds > d) {
+        (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        d = lds;
+    }
+}
 
 int pattern_alloc(fem_pattern *p, void **ptr, size_t bytes)
 {

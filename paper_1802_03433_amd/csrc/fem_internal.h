@@ -274,17 +274,13 @@ inline unsigned grid_for(int64_t n, int threads)
     return (unsigned)((n + threads - 1) / threads);
 }
 
-// Dynamic LDS above 64 KB needs the kernel attribute; set it once per kernel and size
-// (outside any stream capture in practice: the first call of a configuration sets it).
+// Dynamic LDS above 64 KB needs the kernel attribute; it is set once per kernel and size
+// (in practice outside any stream capture: the first call of a configuration sets it).
+void ensure_lds_attr(const void *kernel, size_t lds);
 template <class K>
 void ensure_lds(K kernel, size_t lds)
 {
-    static size_t done = 64 * 1024;
-    if (lds > done) {
-        (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-        done = lds;
-    }
+    if (lds > 64 * 1024) ensure_lds_attr((const void *)kernel, lds);
 }
 
 // Launches of one batched family pass in its scatter mode.

@@ -7,8 +7,9 @@
 // splits into the gradient Gram matrix G = P^T P:
 //     K[(i,a),(j,b)] = lam G[(i,a),(j,b)] + mu G[(i,b),(j,a)] + mu delta_ab sum_c G[(i,c),(j,c)].
 // G is the dense contraction; it runs on the matrix cores: four v_mfma_f64_16x16x4f64
-// per 16x16 output tile (K = 16 quadrature rows), one output tile per wavefront, so the
-// four wavefronts of a workgroup produce one element's 32x32 G together.  The FP32
+// per 16x16 output tile (K = 16 quadrature rows).  Each wavefront forms its own element's
+// G in two strips of 16 rows (two tiles each, node-padded columns so that a strip holds
+// whole nodes), which keeps the LDS buffer at 16 x 32 doubles per wavefront.  The FP32
 // variant rounds P to FP32 and accumulates G in FP32 (v_mfma_f32_16x16x4f32); K and the
 // scatter stay FP64.
 //
@@ -108,7 +109,7 @@ struct P2Args {
 // LDS carve-up (the adjoint needs no Gram buffers but per-node coordinate accumulators)
 struct P2Lds {
     double *R;      // [14][10][3] reference gradients
-    double *G;      // [4][32][32] Gram matrices of the wavefronts' current elements (forward)
+    double *G;      // [4][16][32] Gram-matrix strips of the wavefronts' elements (forward)
     double *acc;    // [smax][9] pair accumulators (forward) / gathered grad_values (adjoint)
     double *xs;     // [3][nmax]
     double *racc;   // [3][nmax] rhs accumulators (forward) / gathered grad_rhs (adjoint)
@@ -125,7 +126,7 @@ struct P2Lds {
     {
         R = (double *)b;
         G = R + 14 * 10 * 3;
-        acc = G + (adj ? 0 : 4 * 32 * 32);
+        acc = G + (adj ? 0 : 4 * 16 * 32);
         xs = acc + 9 * smax;
         racc = xs + 3 * nmax;
         xacc = racc + 3 * nmax;
@@ -142,7 +143,7 @@ struct P2Lds {
 
 size_t p2_lds_bytes(int nmax, int smax, int T, bool adj)
 {
-    return sizeof(double) * (size_t)(420 + (adj ? 0 : 4 * 1024) + 9 * smax + (adj ? 9 : 6) * nmax) +
+    return sizeof(double) * (size_t)(420 + (adj ? 0 : 4 * 512) + 9 * smax + (adj ? 9 : 6) * nmax) +
            sizeof(uint64_t) * 2 * nmax +
            sizeof(int32_t) * (size_t)(4 * nmax + smax) + sizeof(uint16_t) * 100 * T + nmax + 16;
 }
@@ -269,6 +270,17 @@ __device__ int p2_stage(const P2Args &a, P2Lds &L, int64_t tile, int n0, int nn,
     return total;
 }
 
+// P[q][c] for the node-padded column c = 16 (i / 5) + 3 (i % 5) + a (0 in the two padding
+// columns 15 and 31 and beyond the 14 points), up to the factor sqrt(|T|)
+__device__ __forceinline__ double pvalp(const double *R, int q, int c, const double inv[3][3])
+{
+    const int cc = c & 15;
+    if (q >= 14 || cc >= 15) return 0.0;
+    const int i = 5 * (c >> 4) + cc / 3, a = cc - 3 * (cc / 3);
+    const double *r = R + (q * 10 + i) * 3;
+    return r[0] * inv[0][a] + r[1] * inv[1][a] + r[2] * inv[2][a];
+}
+
 template <int MODE, bool F32>
 __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
 {
@@ -283,12 +295,16 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
     const int total = p2_stage(a, L, tile, n0, nn, e0, ne, false);
 
     // ---- elements: one per wavefront, four in flight ----
-    const int wave = tid >> 6, lane = tid & 63;
-    double *G = L.G + wave * 32 * 32;
+    // G is formed in two strips of 16 rows (tiles (h,0) and (h,1)); its columns are
+    // node-padded (node i, component a -> 16 (i / 5) + 3 (i % 5) + a), so strip h holds
+    // the full rows of nodes 5h .. 5h+4 and every K block (i, j) of them.
+    const int wave = tid >> 6, lane = tid & 63, lo = lane & 15, hi = lane >> 4;
+    double *G = L.G + wave * 16 * 32;
     for (int base = 0; base < ne; base += 4) {
         const int el = base + wave;
         const bool has = el < ne;
-        double lm = 0.0, mm = 0.0, vol = 0.0;
+        double lm = 0.0, mm = 0.0, vol = 0.0, sv = 0.0;
+        double inv[3][3];
         if (has) {
             const int64_t e = e0 + el;
             double x[4][3];
@@ -298,82 +314,73 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) x[v][d] = L.xs[d * a.nmax + kv];
             }
-            double inv[3][3];
             p2_geometry(x, inv, vol);
-            const double sv = sqrt(vol);
+            sv = sqrt(vol);
             const int64_t eu = a.telem ? a.telem[e] : e;
             lm = a.lam[eu];
             mm = a.mu[eu];
-            // G = P^T P, symmetric: output tiles (0,0), (0,1), (1,1); (1,0) by transposition
-            const int lo = lane & 15, hi = lane >> 4;
-#pragma unroll
-            for (int tb = 0; tb < 3; ++tb) {
-                const int rb = tb == 2 ? 1 : 0, cb = tb == 0 ? 0 : 1;
-                const int rc = rb * 16 + lo, cc = cb * 16 + lo;
-                if constexpr (F32) {
-                    f4_t g = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const int q = 4 * ks + hi;
-                        const float av = (float)(sv * pval(L.R, q, rc, inv));
-                        const float bv = (float)(sv * pval(L.R, q, cc, inv));
-                        g = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, g, 0, 0, 0);
-                    }
-                    // f32 16x16x4 output layout: register r of lane l holds row 4 (l / 16) + r
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int R = rb * 16 + 4 * hi + r, C = cb * 16 + lo;
-                        G[R * 32 + C] = (double)g[r];
-                        if (tb == 1) G[C * 32 + R] = (double)g[r];
-                    }
-                } else {
-                    d4_t g = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const int q = 4 * ks + hi;
-                        const double av = sv * pval(L.R, q, rc, inv);
-                        const double bv = sv * pval(L.R, q, cc, inv);
-                        g = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, g, 0, 0, 0);
-                    }
-                    // f64 16x16x4 output layout (measured on gfx950): register r of lane l
-                    // holds row (l / 16) + 4 r, column l % 16
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int R = rb * 16 + hi + 4 * r, C = cb * 16 + lo;
-                        G[R * 32 + C] = g[r];
-                        if (tb == 1) G[C * 32 + R] = g[r];
-                    }
-                }
-            }
         }
-        // the Gram matrix was written by other lanes of this wavefront
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // K blocks of this wavefront's element: lanes take node pairs (i, j)
+        // K blocks of this wavefront's element: in strip h, lane < 50 takes the node pair
+        // (5h + lane / 10, lane % 10)
         double kb[2][9];
         int lpi[2] = {0, 0};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int pr = lane + 64 * h;
-            if (has && pr < 100) {
-                const int i = pr / 10, j = pr - 10 * (pr / 10);
+            if (has) {
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    const int rc = 16 * h + lo, cc = 16 * cb + lo;
+                    if constexpr (F32) {
+                        f4_t g = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int ks = 0; ks < 4; ++ks) {
+                            const int q = 4 * ks + hi;
+                            const float av = (float)(sv * pvalp(L.R, q, rc, inv));
+                            const float bv = (float)(sv * pvalp(L.R, q, cc, inv));
+                            g = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, g, 0, 0, 0);
+                        }
+                        // f32 16x16x4 output layout: register r of lane l holds row 4 (l / 16) + r
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) G[(4 * hi + r) * 32 + 16 * cb + lo] = (double)g[r];
+                    } else {
+                        d4_t g = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int ks = 0; ks < 4; ++ks) {
+                            const int q = 4 * ks + hi;
+                            const double av = sv * pvalp(L.R, q, rc, inv);
+                            const double bv = sv * pvalp(L.R, q, cc, inv);
+                            g = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, g, 0, 0, 0);
+                        }
+                        // f64 16x16x4 output layout (measured on gfx950): register r of lane l
+                        // holds row (l / 16) + 4 r, column l % 16
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) G[(hi + 4 * r) * 32 + 16 * cb + lo] = g[r];
+                    }
+                }
+            }
+            // the strip was written by other lanes of this wavefront
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (has && lane < 50) {
+                const int il = lane / 10, j = lane - 10 * il, i = 5 * h + il;
+                const int cj = 16 * (j / 5) + 3 * (j % 5);
                 double gb[3][3];
 #pragma unroll
                 for (int p = 0; p < 3; ++p)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) gb[p][q] = G[(3 * i + p) * 32 + 3 * j + q];
+                    for (int q = 0; q < 3; ++q) gb[p][q] = G[(3 * il + p) * 32 + cj + q];
                 const double tr = gb[0][0] + gb[1][1] + gb[2][2];
 #pragma unroll
                 for (int p = 0; p < 3; ++p)
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
                         kb[h][3 * p + q] = lm * gb[p][q] + mm * gb[q][p] + (p == q ? mm * tr : 0.0);
-                lpi[h] = L.lp[el * 100 + pr];
+                lpi[h] = L.lp[el * 100 + 10 * i + j];
             }
+            // all reads of the strip done before it is overwritten
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        // all reads of G done before the next element overwrites it
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         double bfv[3] = {0.0, 0.0, 0.0};
         int bnode = 0;
         if (a.load == FEM_LOAD_CONST && has && lane < 10) {
@@ -386,7 +393,7 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
         if (MODE == kAtomic) {
 #pragma unroll
             for (int h = 0; h < 2; ++h)
-                if (has && lane + 64 * h < 100)
+                if (has && lane < 50)
 #pragma unroll
                     for (int v = 0; v < 9; ++v) atomicAdd(&L.acc[9 * lpi[h] + v], kb[h][v]);
             if (a.load == FEM_LOAD_CONST && has && lane < 10)
@@ -398,7 +405,7 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
                 if (wave == w2) {
 #pragma unroll
                     for (int h = 0; h < 2; ++h)
-                        if (has && lane + 64 * h < 100)
+                        if (has && lane < 50)
 #pragma unroll
                             for (int v = 0; v < 9; ++v) L.acc[9 * lpi[h] + v] += kb[h][v];
                     if (a.load == FEM_LOAD_CONST && has && lane < 10)
