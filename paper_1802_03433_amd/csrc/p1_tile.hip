@@ -504,9 +504,11 @@ __device__ __forceinline__ void p1_bwd_tile(const TileArgs &a, int64_t tile)
     }
 }
 
-// One mesh: the work item is a tile (through the colour-ordered list unless atomic).
+// One mesh: the work item is a tile (through the colour-ordered list unless atomic).  The
+// forward asks for 5 wavefronts per SIMD (at most 102 registers; it needs 86): more
+// resident tiles hide more of the staging latency.
 template <int D, int LOAD, int MODE>
-__global__ __launch_bounds__(1024) void k_p1_tile_fwd(TileArgs a)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_p1_tile_fwd(TileArgs a)
 {
     __shared__ int s_ticket;
     const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
@@ -524,7 +526,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
 // A batch of meshes: the work item (mesh << 32) | tile comes from the launch's item list
 // and the mesh's arguments from a device table.
 template <int D, int LOAD, int MODE>
-__global__ __launch_bounds__(1024) void k_p1_tile_fwd_batch(const TileArgs *__restrict__ tab,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_p1_tile_fwd_batch(const TileArgs *__restrict__ tab,
                                                             const int64_t *__restrict__ items,
                                                             int32_t *counter)
 {

@@ -645,7 +645,9 @@ __device__ __forceinline__ void p2_bwd_tile(const P2Args &a, int64_t tile)
     }
 }
 
-// One mesh: the work item is a tile (through the colour-ordered list unless atomic).
+// One mesh: the work item is a tile (through the colour-ordered list unless atomic).  The
+// adjoint asks for 3 wavefronts per SIMD (at most 168 registers): its LDS allows 3
+// workgroups per CU.
 template <int MODE, bool F32>
 __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
 {
@@ -655,7 +657,7 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kP2Threads) void k_p2_tile_bwd(P2Args a)
+__global__ __launch_bounds__(kP2Threads) __attribute__((amdgpu_waves_per_eu(3))) void k_p2_tile_bwd(P2Args a)
 {
     __shared__ int s_ticket;
     const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
@@ -675,7 +677,7 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd_batch(const P2Args *
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kP2Threads) void k_p2_tile_bwd_batch(const P2Args *__restrict__ tab,
+__global__ __launch_bounds__(kP2Threads) __attribute__((amdgpu_waves_per_eu(3))) void k_p2_tile_bwd_batch(const P2Args *__restrict__ tab,
                                                                   const int64_t *__restrict__ items,
                                                                   int32_t *counter)
 {
