@@ -115,7 +115,7 @@ def _bench_p2(torch, fem, meshgen, dev, steps):
     out = {"workload": "3D cube 40^3 x 6 P2 tets, isotropic elasticity, body force, 14-point rule",
            "n_elems": E, "nnz": pat.nnz, "pattern_build_ms": build_ms, "n_tile_colours": pat.n_colours}
     for name, kw in (("atomic_f64", {}), ("coloured_f64", {"scatter": "coloured"}),
-                     ("atomic_f32mfma", {"fp32": True})):
+                     ("two_pass_f64", {"scatter": "two-pass"}), ("atomic_f32mfma", {"fp32": True})):
         def step():
             fem.assemble(pat, dm, form, coef, values, rhs, **kw)
         step()
@@ -372,6 +372,12 @@ def main():
 
         step_other()
         extra[f"{other}_ms_per_step"] = _time_calls(torch, step_other, args.steps)
+
+        def step_two_pass():
+            fem.assemble(pat, dm, form, kappa, values, rhs, scatter="two-pass")
+
+        step_two_pass()
+        extra["two_pass_ms_per_step"] = _time_calls(torch, step_two_pass, args.steps)
         form0 = fem.Form("helmholtz", "none", reaction=1.0)
 
         def step_matrix_only():

@@ -80,6 +80,14 @@ extern "C" {
                                      (reference for comparisons); by default the coloured
                                      scatter is one launch in which every tile waits for its
                                      lower-colour neighbours -- same sums, same bits */
+#define FEM_SCATTER_TWO_PASS 0x80u /* deterministic scatter in two passes, without colour
+                                      order: each tile stores its per-slot partial sums
+                                      (elements added in a fixed order), then every slot
+                                      and row sums its partials in ascending tile order.
+                                      Bitwise reproducible run to run.  The first call
+                                      allocates the pattern's partial-sum buffers (not
+                                      under stream capture).  Not combined with
+                                      FEM_SCATTER_COLOURED. */
 /* fem_build_pattern: elements per tile of the combined scatter, as log2 in bits 8..11
    (0 = default: 192 P1 tetrahedra, 256 P1 triangles, 8 P2 tetrahedra; P1 accepts
    multiples of 64 from 64 to 1024, P2 1 to 64), or for P1 as a count of 64-element

@@ -33,6 +33,7 @@ ELEMENT_SCATTER = 0x10
 PREC_FP32 = 0x8
 COLOUR_LAUNCHES = 0x20
 INPUT_ORDER = 0x40
+SCATTER_TWO_PASS = 0x80
 
 
 def TILE_LOG2(k: int) -> int:

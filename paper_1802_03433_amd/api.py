@@ -15,9 +15,11 @@ import torch
 from . import _lib as L
 
 # "coloured": one launch, tiles in colour order; "coloured-launches": one launch per colour
-# (reference; the same sums in the same order, hence the same bits)
+# (reference; the same sums in the same order, hence the same bits); "two-pass": tile
+# partial sums, then a fixed-order sum per slot (deterministic, no colour order)
 _SCATTER = {"atomic": L.SCATTER_ATOMIC, "coloured": L.SCATTER_COLOURED,
-            "coloured-launches": L.SCATTER_COLOURED | L.COLOUR_LAUNCHES}
+            "coloured-launches": L.SCATTER_COLOURED | L.COLOUR_LAUNCHES,
+            "two-pass": L.SCATTER_TWO_PASS}
 
 
 def _stream_ptr(device) -> ctypes.c_void_p:

@@ -63,6 +63,18 @@ int check_form(const fem_pattern *p, const fem_form *f)
     return fail(FEM_ERR_INVALID_ARG, "unknown form kind");
 }
 
+int check_scatter_flags(const fem_pattern *p, unsigned flags)
+{
+    if (!(flags & FEM_SCATTER_TWO_PASS)) return FEM_OK;
+    if (flags & (FEM_SCATTER_COLOURED | FEM_COLOUR_LAUNCHES))
+        return fail(FEM_ERR_INVALID_ARG, "FEM_SCATTER_TWO_PASS excludes the coloured scatter");
+    if (flags & FEM_ELEMENT_SCATTER)
+        return fail(FEM_ERR_UNSUPPORTED, "the two-pass scatter works on tiles");
+    if (p->n_elems > 0 && !p->has_tiles)
+        return fail(FEM_ERR_UNSUPPORTED, "the two-pass scatter needs the tile plan");
+    return FEM_OK;
+}
+
 }  // namespace fem
 
 extern "C" {
@@ -233,8 +245,9 @@ int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *for
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));
     if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER |
-                  FEM_PREC_FP32 | FEM_COLOUR_LAUNCHES))
+                  FEM_PREC_FP32 | FEM_COLOUR_LAUNCHES | FEM_SCATTER_TWO_PASS))
         return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
+    FEM_TRY(check_scatter_flags(p, flags));
     if (!values && p->nnz > 0) return fail(FEM_ERR_INVALID_ARG, "values is NULL");
     if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
     if (form->load != FEM_LOAD_NONE && !rhs && p->n_rows > 0)
@@ -254,9 +267,11 @@ int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *for
         return fail(FEM_ERR_UNSUPPORTED, "per-element coloured scatter needs an element colouring");
     if (!accumulate) {
         // the coloured tile scatter stores (rather than adds) on its first write of every
-        // slot, so only the RHS of nodes in no element needs clearing
-        if (!(tiles && coloured)) FEM_TRY(fill_zero_f64(values, p->nnz, s));
-        if (rhs_ok && (!(tiles && coloured) || p->has_isolated_nodes))
+        // slot, so only the RHS of nodes in no element needs clearing; the two-pass
+        // scatter writes every slot and row
+        const bool two_pass = (flags & FEM_SCATTER_TWO_PASS) != 0;
+        if (!(tiles && (coloured || two_pass))) FEM_TRY(fill_zero_f64(values, p->nnz, s));
+        if (rhs_ok && !two_pass && (!(tiles && coloured) || p->has_isolated_nodes))
             FEM_TRY(fill_zero_f64(rhs_ok, p->n_rows, s));
     }
     if (elast) return p2_tile_forward(p, mesh, form, coef, values, rhs_ok, flags, s);
@@ -273,8 +288,9 @@ int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));
     if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_ELEMENT_SCATTER |
-                  FEM_PREC_FP32 | FEM_COLOUR_LAUNCHES))
+                  FEM_PREC_FP32 | FEM_COLOUR_LAUNCHES | FEM_SCATTER_TWO_PASS))
         return fail(FEM_ERR_INVALID_ARG, "unknown flag bits");
+    FEM_TRY(check_scatter_flags(p, flags));
     if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
     hipStream_t s = (hipStream_t)stream;
     const bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
@@ -287,7 +303,8 @@ int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_
     const bool tiles = p->has_tiles && !(flags & FEM_ELEMENT_SCATTER);
     if (!tiles && coloured && !p->has_element_colouring)
         return fail(FEM_ERR_UNSUPPORTED, "per-element coloured scatter needs an element colouring");
-    if (!accumulate && grad_coords && (!(tiles && coloured) || p->has_isolated_nodes))
+    if (!accumulate && grad_coords && !(flags & FEM_SCATTER_TWO_PASS) &&
+        (!(tiles && coloured) || p->has_isolated_nodes))
         FEM_TRY(fill_zero_f64(grad_coords, p->dim * p->n_nodes, s));
     if (!grad_coef && !grad_coords) return FEM_OK;
     const double *grhs = (form->load == FEM_LOAD_NONE) ? nullptr : grad_rhs;

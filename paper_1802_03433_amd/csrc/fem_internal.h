@@ -47,10 +47,12 @@ inline int fail(int code, const std::string &msg)
 // kAtomic: device-scope FP64 atomics.  kColoured: one launch per tile colour, plain
 // read-modify-writes.  kOrdered: one launch, tiles in colour order waiting for their
 // lower-colour neighbours, coherent read-modify-writes (same sums as kColoured).
-enum ScatterMode : int { kAtomic = 0, kColoured = 1, kOrdered = 2 };
+// kTwoPass: per-tile partial sums stored, then summed per slot in tile order.
+enum ScatterMode : int { kAtomic = 0, kColoured = 1, kOrdered = 2, kTwoPass = 3 };
 
 inline int scatter_mode(unsigned flags)
 {
+    if (flags & FEM_SCATTER_TWO_PASS) return kTwoPass;
     if (!(flags & FEM_SCATTER_COLOURED)) return kAtomic;
     return (flags & FEM_COLOUR_LAUNCHES) ? kColoured : kOrdered;
 }
@@ -139,6 +141,16 @@ struct fem_pattern {
     int32_t *tpred_ptr = nullptr;  // [n_tiles+1]
     int32_t *tpred = nullptr;
     int32_t *tctrl = nullptr;
+    // two-pass scatter: partial j is tile entry j of tslot (slot partials) or of tnode (row
+    // partials); pslot lists, per node-level slot, its partials in ascending j (= tile)
+    // order, pnode the same per node.  Partial buffers are allocated on first use.
+    int64_t n_tslots = 0, n_tnodes = 0;
+    int32_t *pslot_ptr = nullptr;  // [nnz_nodes+1]
+    int32_t *pslot_idx = nullptr;  // [n_tslots]
+    int32_t *pnode_ptr = nullptr;  // [n_nodes+1]
+    int32_t *pnode_idx = nullptr;  // [n_tnodes]
+    double *part = nullptr;        // [n_tslots * (P1: 1, P2: 9)]
+    double *rpart = nullptr;       // [3][n_tnodes]
     std::vector<fem::DevBuf> owned;
     int64_t device_bytes = 0;
 };
@@ -257,6 +269,19 @@ int npe_of(int dim, int order);
 int check_mesh(const fem_mesh *m, bool need_coords);
 int check_same_mesh(const fem_pattern *p, const fem_mesh *m);
 int check_form(const fem_pattern *p, const fem_form *f);
+int check_scatter_flags(const fem_pattern *p, unsigned flags);
+
+// two-pass scatter (reduce.hip): partial-sum buffers (allocated once, not under capture)
+// and the per-slot / per-node sums in tile order
+int ensure_partials(fem_pattern *p, hipStream_t s);
+// values[k] (+)= sum of part over slot k's list (P1 / scalar: one value per slot)
+int reduce_slots(const fem_pattern *p, double *values, bool accumulate, hipStream_t s);
+// P2: 9 dof-level values per node-level slot
+int reduce_pair_slots(const fem_pattern *p, double *values, bool accumulate, hipStream_t s);
+// out (+)= per-node sums of rpart for ncomp components; out index c * N + n (planar) or
+// ncomp * n + c (interleaved)
+int reduce_nodes(const fem_pattern *p, int ncomp, bool interleaved, double *out, bool accumulate,
+                 hipStream_t s);
 
 // device check of the element Jacobians (p1.hip; reads the vertex coordinates only)
 int validate_elements(const fem_mesh *m, hipStream_t s);

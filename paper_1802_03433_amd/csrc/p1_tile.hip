@@ -46,6 +46,9 @@ struct TileArgs {
     bool use_first;
     // forward
     double *values, *rhs;
+    // two-pass scatter: tile partials (slot entries, row entries [D][n_tnodes])
+    double *part, *rpart;
+    int64_t n_tnodes;
     // adjoint
     const double *gvalues, *grhs;
     double *gkappa, *gcoords;
@@ -191,6 +194,68 @@ __device__ __forceinline__ void qpoint(const Elem<D> &g, int q, double *xq)
     }
 }
 
+// One element of a staged tile (Alg. 1's per-element steps): vertex coordinates from the
+// tile's LDS, geometry, the element matrix A (stiffness + mass, exact for affine
+// elements), the tile-local slot index of each entry, and the load vector by the rule.
+template <int D, int LOAD>
+__device__ __forceinline__ void p1_element(const TileArgs &a, const Lds<D> &L, uint64_t en,
+                                           const uint32_t pr[D + 1], double kap,
+                                           double A[D + 1][D + 1], double bv[D + 1], int ki[D + 1],
+                                           int li[D + 1][D + 1])
+{
+    constexpr int NP = D + 1;
+    using R = quad::P1Rule<D>;
+    Elem<D> g;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        ki[k] = (int)((en >> (16 * k)) & 0xffffu);
+#pragma unroll
+        for (int d = 0; d < D; ++d) g.x[k][d] = L.xs[d * a.nmax + ki[k]];
+    }
+    elem_geometry<D>(g);
+    const double kv = kap * g.vol, cv = a.c * g.vol;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int j = i; j < NP; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) s += g.B[i][d] * g.B[j][d];
+            A[i][j] = kv * s + cv * quad::p1_mass<D>(i, j);
+            A[j][i] = A[i][j];
+        }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const uint64_t r = L.rb[ki[i]];
+        const int base = L.ust[ki[i]];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int p = (int)((pr[i] >> (8 * j)) & 0xffu);
+            li[i][j] = base + __popcll(r & ((1ull << p) - 1ull));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) bv[i] = 0.0;
+    if constexpr (LOAD != FEM_LOAD_NONE) {
+#pragma unroll
+        for (int q = 0; q < R::nq; ++q) {
+            double f;
+            if constexpr (LOAD == FEM_LOAD_SINPROD) {
+                double xq[D];
+                qpoint<D>(g, q, xq);
+                f = 1.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) f *= fem_sinpi(xq[d]);
+            } else {
+                f = a.fconst;
+            }
+            const double wf = g.vol * R::w(q) * f;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) bv[i] += wf * R::lam(q, i);
+        }
+    }
+}
+
 template <int D, int LOAD, int MODE>
 __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
 {
@@ -219,57 +284,7 @@ __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
 
     double A[NP][NP], bv[NP];
     int ki[NP], li[NP][NP];
-    if (active) {
-        Elem<D> g;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            ki[k] = (int)((en >> (16 * k)) & 0xffffu);
-#pragma unroll
-            for (int d = 0; d < D; ++d) g.x[k][d] = L.xs[d * a.nmax + ki[k]];
-        }
-        elem_geometry<D>(g);
-        const double kv = kap * g.vol, cv = a.c * g.vol;
-#pragma unroll
-        for (int i = 0; i < NP; ++i)
-#pragma unroll
-            for (int j = i; j < NP; ++j) {
-                double s = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) s += g.B[i][d] * g.B[j][d];
-                A[i][j] = kv * s + cv * quad::p1_mass<D>(i, j);
-                A[j][i] = A[i][j];
-            }
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            const uint64_t r = L.rb[ki[i]];
-            const int base = L.ust[ki[i]];
-#pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                const int p = (int)((pr[i] >> (8 * j)) & 0xffu);
-                li[i][j] = base + __popcll(r & ((1ull << p) - 1ull));
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < NP; ++i) bv[i] = 0.0;
-        if constexpr (LOAD != FEM_LOAD_NONE) {
-#pragma unroll
-            for (int q = 0; q < R::nq; ++q) {
-                double f;
-                if constexpr (LOAD == FEM_LOAD_SINPROD) {
-                    double xq[D];
-                    qpoint<D>(g, q, xq);
-                    f = 1.0;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) f *= fem_sinpi(xq[d]);
-                } else {
-                    f = a.fconst;
-                }
-                const double wf = g.vol * R::w(q) * f;
-#pragma unroll
-                for (int i = 0; i < NP; ++i) bv[i] += wf * R::lam(q, i);
-            }
-        }
-    }
+    if (active) p1_element<D, LOAD>(a, L, en, pr, kap, A, bv, ki, li);
     if (MODE == kAtomic) {
         if (active) {
 #pragma unroll
@@ -304,6 +319,15 @@ __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
                 a.rhs, nn, [&](int k) { return L.nd[k]; }, [&](int k) { return L.nacc[k]; },
                 [&](int k) { return L.nf[k] != 0; });
         publish_done(a.flags, tile);
+        return;
+    }
+    if (MODE == kTwoPass) {
+        const int64_t j0 = a.tslot_ptr[tile];
+        for (int u = threadIdx.x; u < ns; u += blockDim.x) a.part[j0 + u] = L.sacc[u];
+        if (LOAD != FEM_LOAD_NONE) {
+            const int64_t r0 = a.tnode_ptr[tile];
+            for (int k = threadIdx.x; k < nn; k += blockDim.x) a.rpart[r0 + k] = L.nacc[k];
+        }
         return;
     }
     for (int u = threadIdx.x; u < ns; u += blockDim.x) {
@@ -491,6 +515,13 @@ __device__ __forceinline__ void p1_bwd_tile(const TileArgs &a, int64_t tile)
         publish_done(a.flags, tile);
         return;
     }
+    if (MODE == kTwoPass) {
+        const int64_t r0 = a.tnode_ptr[tile];
+        for (int k = threadIdx.x; k < nn; k += blockDim.x)
+#pragma unroll
+            for (int d = 0; d < D; ++d) a.rpart[d * a.n_tnodes + r0 + k] = L.nacc[d * a.nmax + k];
+        return;
+    }
     for (int k = threadIdx.x; k < nn; k += blockDim.x) {
         const int32_t n = L.nd[k];
 #pragma unroll
@@ -512,7 +543,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void 
 {
     __shared__ int s_ticket;
     const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
-    p1_fwd_tile<D, LOAD, MODE>(a, MODE == kAtomic ? i : a.tile_list[i]);
+    p1_fwd_tile<D, LOAD, MODE>(a, (MODE == kAtomic || MODE == kTwoPass) ? i : a.tile_list[i]);
 }
 
 template <int D, int LOAD, int MODE>
@@ -520,7 +551,7 @@ __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
 {
     __shared__ int s_ticket;
     const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
-    p1_bwd_tile<D, LOAD, MODE>(a, MODE == kAtomic ? i : a.tile_list[i]);
+    p1_bwd_tile<D, LOAD, MODE>(a, (MODE == kAtomic || MODE == kTwoPass) ? i : a.tile_list[i]);
 }
 
 // A batch of meshes: the work item (mesh << 32) | tile comes from the launch's item list
@@ -564,6 +595,9 @@ TileArgs base_args(const fem_pattern *p, const fem_mesh *m, const fem_form *f, c
     a.esub = p->esub;
     a.tile_nsub = p->tile_nsub;
     a.telem = p->telem;
+    a.part = p->part;
+    a.rpart = p->rpart;
+    a.n_tnodes = p->n_tnodes;
     a.tust = p->tust;
     a.tslot_ptr = p->tslot_ptr;
     a.tslot = p->tslot;
@@ -584,7 +618,7 @@ template <class K>
 void launch(K kernel, const fem_pattern *p, TileArgs a, int mode, size_t lds, hipStream_t s)
 {
     ensure_lds(kernel, lds);
-    if (mode == kAtomic) {
+    if (mode == kAtomic || mode == kTwoPass) {
         a.tile_list = nullptr;
         hipLaunchKernelGGL(kernel, dim3((unsigned)p->n_tiles), dim3(p->tile), lds, s, a);
         return;
@@ -609,6 +643,7 @@ int fwd_d(const fem_pattern *p, TileArgs a, int mode, hipStream_t s)
     size_t lds = lds_bytes<D>(a.nmax, a.smax);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
     if (mode == kOrdered) launch(k_p1_tile_fwd<D, LOAD, kOrdered>, p, a, mode, lds, s);
+    else if (mode == kTwoPass) launch(k_p1_tile_fwd<D, LOAD, kTwoPass>, p, a, mode, lds, s);
     else if (mode == kColoured) launch(k_p1_tile_fwd<D, LOAD, kColoured>, p, a, mode, lds, s);
     else launch(k_p1_tile_fwd<D, LOAD, kAtomic>, p, a, mode, lds, s);
     return FEM_OK;
@@ -620,6 +655,7 @@ int bwd_d(const fem_pattern *p, TileArgs a, int mode, hipStream_t s)
     size_t lds = lds_bytes<D>(a.nmax, a.smax);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
     if (mode == kOrdered) launch(k_p1_tile_bwd<D, LOAD, kOrdered>, p, a, mode, lds, s);
+    else if (mode == kTwoPass) launch(k_p1_tile_bwd<D, LOAD, kTwoPass>, p, a, mode, lds, s);
     else if (mode == kColoured) launch(k_p1_tile_bwd<D, LOAD, kColoured>, p, a, mode, lds, s);
     else launch(k_p1_tile_bwd<D, LOAD, kAtomic>, p, a, mode, lds, s);
     return FEM_OK;
@@ -725,14 +761,20 @@ int p1_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
 {
     if (p->n_tiles == 0) return FEM_OK;
     const int mode = scatter_mode(flags);
+    if (mode == kTwoPass) FEM_TRY(ensure_partials(const_cast<fem_pattern *>(p), s));
     TileArgs a = (m->dim == 2) ? base_args<2>(p, m, f, coef) : base_args<3>(p, m, f, coef);
     a.values = values;
     a.rhs = rhs;
-    a.use_first = mode != kAtomic && !(flags & FEM_ACCUMULATE);
+    a.use_first = (mode == kColoured || mode == kOrdered) && !(flags & FEM_ACCUMULATE);
     const int load = rhs ? f->load : FEM_LOAD_NONE;
     int rc = (m->dim == 2) ? fwd_load<2>(p, a, load, mode, s) : fwd_load<3>(p, a, load, mode, s);
     if (rc != FEM_OK) return rc;
     FEM_HIP_TRY(hipGetLastError());
+    if (mode == kTwoPass) {
+        const bool acc = (flags & FEM_ACCUMULATE) != 0;
+        FEM_TRY(reduce_slots(p, values, acc, s));
+        if (load != FEM_LOAD_NONE) FEM_TRY(reduce_nodes(p, 1, false, rhs, acc, s));
+    }
     return FEM_OK;
 }
 
@@ -742,17 +784,19 @@ int p1_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
 {
     if (p->n_tiles == 0) return FEM_OK;
     const int mode = scatter_mode(flags);
+    if (mode == kTwoPass) FEM_TRY(ensure_partials(const_cast<fem_pattern *>(p), s));
     TileArgs a = (m->dim == 2) ? base_args<2>(p, m, f, coef) : base_args<3>(p, m, f, coef);
     a.gvalues = gvalues;
     a.grhs = grhs;
     a.gkappa = gcoef;
     a.gcoords = gcoords;
     a.accumulate = (flags & FEM_ACCUMULATE) != 0;
-    a.use_first = mode != kAtomic && !a.accumulate;
+    a.use_first = (mode == kColoured || mode == kOrdered) && !a.accumulate;
     const int load = grhs ? f->load : FEM_LOAD_NONE;
     int rc = (m->dim == 2) ? bwd_load<2>(p, a, load, mode, s) : bwd_load<3>(p, a, load, mode, s);
     if (rc != FEM_OK) return rc;
     FEM_HIP_TRY(hipGetLastError());
+    if (mode == kTwoPass && gcoords) FEM_TRY(reduce_nodes(p, m->dim, false, gcoords, a.accumulate, s));
     return FEM_OK;
 }
 

@@ -98,6 +98,9 @@ struct P2Args {
     int load;
     double bf[3];
     double *values, *rhs;
+    // two-pass scatter: tile partials (9 per pair entry; rows [3][n_tnodes])
+    double *part, *rpart;
+    int64_t n_tnodes;
     // adjoint
     const double *gvalues, *grhs;
     double *gcoef, *gcoords;
@@ -437,6 +440,16 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
         publish_done(a.flags, tile);
         return;
     }
+    if (MODE == kTwoPass) {
+        const int64_t j0 = a.tslot_ptr[tile], r0 = a.tnode_ptr[tile];
+        for (int t = tid; t < nvals; t += kP2Threads) a.part[9 * j0 + t] = L.acc[t];
+        if (a.load == FEM_LOAD_CONST)
+            for (int t = tid; t < 3 * nn; t += kP2Threads) {
+                const int c = t / nn, k = t - c * nn;
+                a.rpart[c * a.n_tnodes + r0 + k] = L.racc[c * a.nmax + k];
+            }
+        return;
+    }
     for (int t = tid; t < nvals; t += kP2Threads) {
         const PairValue pv(t, total);
         const int64_t slot = pair_slot(L, pv);
@@ -635,6 +648,14 @@ __device__ __forceinline__ void p2_bwd_tile(const P2Args &a, int64_t tile)
         publish_done(a.flags, tile);
         return;
     }
+    if (MODE == kTwoPass) {
+        const int64_t r0 = a.tnode_ptr[tile];
+        for (int t = tid; t < 3 * nn; t += kP2Threads) {
+            const int d = t / nn, k = t - d * nn;
+            a.rpart[d * a.n_tnodes + r0 + k] = L.xacc[d * a.nmax + k];
+        }
+        return;
+    }
     for (int t = tid; t < 3 * nn; t += kP2Threads) {
         const int d = t / nn, k = t - d * nn;
         double *dst = a.gcoords + d * a.N + L.nd[k];
@@ -653,7 +674,7 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd(P2Args a)
 {
     __shared__ int s_ticket;
     const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
-    p2_fwd_tile<MODE, F32>(a, MODE == kAtomic ? i : a.tile_list[i]);
+    p2_fwd_tile<MODE, F32>(a, (MODE == kAtomic || MODE == kTwoPass) ? i : a.tile_list[i]);
 }
 
 template <int MODE>
@@ -661,7 +682,7 @@ __global__ __launch_bounds__(kP2Threads) __attribute__((amdgpu_waves_per_eu(3)))
 {
     __shared__ int s_ticket;
     const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
-    p2_bwd_tile<MODE>(a, MODE == kAtomic ? i : a.tile_list[i]);
+    p2_bwd_tile<MODE>(a, (MODE == kAtomic || MODE == kTwoPass) ? i : a.tile_list[i]);
 }
 
 // A batch of meshes: the work item (mesh << 32) | tile comes from the launch's item list
@@ -690,7 +711,7 @@ template <class K>
 void p2_launch(K kernel, const fem_pattern *p, P2Args a, int mode, size_t lds, hipStream_t s)
 {
     ensure_lds(kernel, lds);
-    if (mode == kAtomic) {
+    if (mode == kAtomic || mode == kTwoPass) {
         a.tile_list = nullptr;
         hipLaunchKernelGGL(kernel, dim3((unsigned)p->n_tiles), dim3(kP2Threads), lds, s, a);
         return;
@@ -733,6 +754,9 @@ P2Args p2_args(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const
     a.enode = p->enode16;
     a.epos = p->epos8;
     a.telem = p->telem;
+    a.part = p->part;
+    a.rpart = p->rpart;
+    a.n_tnodes = p->n_tnodes;
     a.pred_ptr = p->tpred_ptr;
     a.pred = p->tpred;
     a.flags = p->tctrl;
@@ -811,11 +835,12 @@ int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
 {
     if (p->n_tiles == 0) return FEM_OK;
     const int mode = scatter_mode(flags);
+    if (mode == kTwoPass) FEM_TRY(ensure_partials(const_cast<fem_pattern *>(p), s));
     P2Args a = p2_args(p, m, f, coef);
     a.load = rhs ? f->load : FEM_LOAD_NONE;
     a.values = values;
     a.rhs = rhs;
-    a.use_first = mode != kAtomic && !(flags & FEM_ACCUMULATE);
+    a.use_first = (mode == kColoured || mode == kOrdered) && !(flags & FEM_ACCUMULATE);
     if (a.T > 64) return fail(FEM_ERR_UNSUPPORTED, "P2 tiles hold at most 64 elements");
     const size_t lds = p2_lds_bytes(a.nmax, a.smax, a.T, false);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "P2 tile needs more LDS than a CU has");
@@ -826,11 +851,19 @@ int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
     } else if (mode == kColoured) {
         if (f32) p2_launch(k_p2_tile_fwd<kColoured, true>, p, a, mode, lds, s);
         else p2_launch(k_p2_tile_fwd<kColoured, false>, p, a, mode, lds, s);
+    } else if (mode == kTwoPass) {
+        if (f32) p2_launch(k_p2_tile_fwd<kTwoPass, true>, p, a, mode, lds, s);
+        else p2_launch(k_p2_tile_fwd<kTwoPass, false>, p, a, mode, lds, s);
     } else {
         if (f32) p2_launch(k_p2_tile_fwd<kAtomic, true>, p, a, mode, lds, s);
         else p2_launch(k_p2_tile_fwd<kAtomic, false>, p, a, mode, lds, s);
     }
     FEM_HIP_TRY(hipGetLastError());
+    if (mode == kTwoPass) {
+        const bool acc = (flags & FEM_ACCUMULATE) != 0;
+        FEM_TRY(reduce_pair_slots(p, values, acc, s));
+        if (a.load == FEM_LOAD_CONST) FEM_TRY(reduce_nodes(p, 3, true, rhs, acc, s));
+    }
     return FEM_OK;
 }
 
@@ -840,6 +873,7 @@ int p2_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
 {
     if (p->n_tiles == 0) return FEM_OK;
     const int mode = scatter_mode(flags);
+    if (mode == kTwoPass) FEM_TRY(ensure_partials(const_cast<fem_pattern *>(p), s));
     P2Args a = p2_args(p, m, f, coef);
     a.load = grhs ? f->load : FEM_LOAD_NONE;
     a.gvalues = gvalues;
@@ -847,14 +881,16 @@ int p2_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
     a.gcoef = gcoef;
     a.gcoords = gcoords;
     a.accumulate = (flags & FEM_ACCUMULATE) != 0;
-    a.use_first = mode != kAtomic && !a.accumulate;
+    a.use_first = (mode == kColoured || mode == kOrdered) && !a.accumulate;
     if (a.T > 64) return fail(FEM_ERR_UNSUPPORTED, "P2 tiles hold at most 64 elements");
     const size_t lds = p2_lds_bytes(a.nmax, a.smax, a.T, true);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "P2 tile needs more LDS than a CU has");
     if (mode == kOrdered) p2_launch(k_p2_tile_bwd<kOrdered>, p, a, mode, lds, s);
     else if (mode == kColoured) p2_launch(k_p2_tile_bwd<kColoured>, p, a, mode, lds, s);
+    else if (mode == kTwoPass) p2_launch(k_p2_tile_bwd<kTwoPass>, p, a, mode, lds, s);
     else p2_launch(k_p2_tile_bwd<kAtomic>, p, a, mode, lds, s);
     FEM_HIP_TRY(hipGetLastError());
+    if (mode == kTwoPass && gcoords) FEM_TRY(reduce_nodes(p, 3, false, gcoords, a.accumulate, s));
     return FEM_OK;
 }
 

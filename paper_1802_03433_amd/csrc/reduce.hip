@@ -1,0 +1,123 @@
+// Second pass of the two-pass deterministic scatter.
+//
+// The first pass (the tile kernels in two-pass mode) stores, for every tile, the sum of
+// its elements' contributions to each distinct slot and node row -- elements added in the
+// tile's fixed intra-tile order -- at the tile's entry positions (coalesced, no atomics,
+// no waiting between tiles).  Here every slot and row adds its tile partials in ascending
+// tile order through the precomputed lists, so every output is a fixed sum: bitwise
+// reproducible, whatever the launch order.
+#include "fem_internal.h"
+
+namespace fem {
+
+namespace {
+
+constexpr int kRT = 256;
+
+__global__ void k_reduce_slots(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                               const double *__restrict__ part, int64_t nslots,
+                               double *__restrict__ values, bool accumulate)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nslots) return;
+    double s = 0.0;
+    for (int32_t i = ptr[k]; i < ptr[k + 1]; ++i) s += part[idx[i]];
+    values[k] = accumulate ? values[k] + s : s;
+}
+
+// P2: node-level slot k = (node n, row position p); its 9 dof-level values
+// 9 rowptr[n] + 3 a L_n + 3 p + b, partial j holds them at 9 j + 3 a + b
+__global__ void k_reduce_pair_slots(const int32_t *__restrict__ rowptr, int64_t n_nodes,
+                                    const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                    const double *__restrict__ part, int64_t nslots,
+                                    double *__restrict__ values, bool accumulate)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nslots) return;
+    // row of slot k: the last n with rowptr[n] <= k
+    int64_t lo = 0, hi = n_nodes;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (rowptr[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    const int64_t n = lo;
+    const int64_t L = rowptr[n + 1] - rowptr[n], pos = k - rowptr[n];
+    double s[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) s[v] = 0.0;
+    for (int32_t i = ptr[k]; i < ptr[k + 1]; ++i) {
+        const double *q = part + 9 * (int64_t)idx[i];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) s[v] += q[v];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double *dst = values + 9 * (int64_t)rowptr[n] + 3 * a * L + 3 * pos + b;
+            *dst = accumulate ? *dst + s[3 * a + b] : s[3 * a + b];
+        }
+}
+
+__global__ void k_reduce_nodes(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                               const double *__restrict__ rpart, int64_t n_tnodes, int64_t n_nodes,
+                               int ncomp, bool interleaved, double *__restrict__ out, bool accumulate)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0.0;
+        for (int32_t i = ptr[n]; i < ptr[n + 1]; ++i) s += rpart[c * n_tnodes + idx[i]];
+        double *dst = out + (interleaved ? ncomp * n + c : c * n_nodes + n);
+        *dst = accumulate ? *dst + s : s;
+    }
+}
+
+}  // namespace
+
+int ensure_partials(fem_pattern *p, hipStream_t s)
+{
+    if (p->part && p->rpart) return FEM_OK;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    FEM_HIP_TRY(hipStreamIsCapturing(s, &st));
+    if (st != hipStreamCaptureStatusNone)
+        return fail(FEM_ERR_UNSUPPORTED, "the two-pass scatter allocates its partial sums on the "
+                                         "first call: make one call before capturing");
+    const int per = (p->order == 2) ? 9 : 1;
+    if (!p->part) FEM_TRY(pattern_alloc(p, (void **)&p->part, sizeof(double) * per * p->n_tslots));
+    if (!p->rpart) FEM_TRY(pattern_alloc(p, (void **)&p->rpart, sizeof(double) * 3 * p->n_tnodes));
+    return FEM_OK;
+}
+
+int reduce_slots(const fem_pattern *p, double *values, bool accumulate, hipStream_t s)
+{
+    if (p->nnz_nodes == 0) return FEM_OK;
+    hipLaunchKernelGGL(k_reduce_slots, dim3(grid_for(p->nnz_nodes, kRT)), dim3(kRT), 0, s,
+                       p->pslot_ptr, p->pslot_idx, p->part, p->nnz_nodes, values, accumulate);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+int reduce_pair_slots(const fem_pattern *p, double *values, bool accumulate, hipStream_t s)
+{
+    if (p->nnz_nodes == 0) return FEM_OK;
+    hipLaunchKernelGGL(k_reduce_pair_slots, dim3(grid_for(p->nnz_nodes, kRT)), dim3(kRT), 0, s,
+                       p->rowptr_n, p->n_nodes, p->pslot_ptr, p->pslot_idx, p->part, p->nnz_nodes,
+                       values, accumulate);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+int reduce_nodes(const fem_pattern *p, int ncomp, bool interleaved, double *out, bool accumulate,
+                 hipStream_t s)
+{
+    if (p->n_nodes == 0) return FEM_OK;
+    hipLaunchKernelGGL(k_reduce_nodes, dim3(grid_for(p->n_nodes, kRT)), dim3(kRT), 0, s,
+                       p->pnode_ptr, p->pnode_idx, p->rpart, p->n_tnodes, p->n_nodes, ncomp,
+                       interleaved, out, accumulate);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+}  // namespace fem

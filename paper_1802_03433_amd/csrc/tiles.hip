@@ -511,6 +511,83 @@ int scan_to_i32(TmpT &tmp, const int32_t *cnt, int64_t n, int32_t *out, int64_t 
     return FEM_OK;
 }
 
+// Two-pass scatter lists.  key of tile slot entry j: its node-level CSR slot (P1: the
+// entry itself; P2: rowptr of its tile node + its row position).
+template <bool PACKED>
+__global__ __launch_bounds__(kTT) void k_tslot_keys(const int32_t *__restrict__ tnode_ptr,
+                                                    const int32_t *__restrict__ tnode,
+                                                    const int64_t *__restrict__ tslot_ptr,
+                                                    const int32_t *__restrict__ tslot,
+                                                    const int32_t *__restrict__ rowptr,
+                                                    int32_t *__restrict__ keys)
+{
+    const int64_t t = blockIdx.x;
+    const int64_t s0 = tslot_ptr[t];
+    const int ns = (int)(tslot_ptr[t + 1] - s0);
+    for (int u = threadIdx.x; u < ns; u += kTT) {
+        const int32_t code = tslot[s0 + u];
+        if (PACKED) {
+            keys[s0 + u] = code < 0 ? ~code : code;
+        } else {
+            const int k = (code >> 8) & 0xffff, pos = code & 0xff;
+            keys[s0 + u] = rowptr[tnode[tnode_ptr[t] + k]] + pos;
+        }
+    }
+}
+
+__global__ void k_key_count(const int32_t *__restrict__ keys, int64_t n, int32_t *__restrict__ cnt)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) atomicAdd(&cnt[keys[j]], 1);
+}
+
+__global__ void k_key_fill(const int32_t *__restrict__ keys, int64_t n, int32_t *__restrict__ cur,
+                           int32_t *__restrict__ idx)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) idx[atomicAdd(&cur[keys[j]], 1)] = (int32_t)j;
+}
+
+// each key's list in ascending entry order (the fill order above is arbitrary)
+__global__ void k_key_sort(const int32_t *__restrict__ ptr, int64_t nkeys, int32_t *__restrict__ idx)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nkeys) return;
+    for (int32_t i = ptr[k] + 1; i < ptr[k + 1]; ++i) {
+        const int32_t v = idx[i];
+        int32_t j = i - 1;
+        while (j >= ptr[k] && idx[j] > v) {
+            idx[j + 1] = idx[j];
+            --j;
+        }
+        idx[j + 1] = v;
+    }
+}
+
+int build_lists(fem_pattern *p, TmpT &tmp, const int32_t *keys, int64_t n, int64_t nkeys,
+                int32_t **ptr_out, int32_t **idx_out, hipStream_t s)
+{
+    int32_t *cnt = nullptr, *cur = nullptr;
+    FEM_TRY(tmp.get(&cnt, nkeys));
+    FEM_TRY(fill_zero_i32(cnt, nkeys, s));
+    if (n > 0)
+        hipLaunchKernelGGL(k_key_count, dim3(grid_for(n, kTT)), dim3(kTT), 0, s, keys, n, cnt);
+    FEM_TRY(pattern_alloc(p, (void **)ptr_out, sizeof(int32_t) * (nkeys + 1)));
+    int64_t total = 0;
+    FEM_TRY(scan_to_i32(tmp, cnt, nkeys, *ptr_out, &total, s));
+    if (total != n) return fail(FEM_ERR_HIP, "internal: partial lists do not cover every entry");
+    FEM_TRY(pattern_alloc(p, (void **)idx_out, sizeof(int32_t) * n));
+    FEM_TRY(tmp.get(&cur, nkeys + 1));
+    FEM_HIP_TRY(hipMemcpyAsync(cur, *ptr_out, sizeof(int32_t) * (nkeys + 1), hipMemcpyDeviceToDevice, s));
+    if (n > 0)
+        hipLaunchKernelGGL(k_key_fill, dim3(grid_for(n, kTT)), dim3(kTT), 0, s, keys, n, cur, *idx_out);
+    if (nkeys > 0)
+        hipLaunchKernelGGL(k_key_sort, dim3(grid_for(nkeys, kTT)), dim3(kTT), 0, s, *ptr_out, nkeys,
+                           *idx_out);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
 }  // namespace
 
 int build_tile_plan(fem_pattern *p, const int32_t *conn, const int32_t *slot, const int32_t *n2e,
@@ -651,6 +728,24 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, const int32_t *slot, co
             hipLaunchKernelGGL((k_tile_slots<true, 2, false>), dim3((unsigned)nt), dim3(kTT), 0, s,
                                p->tnode_ptr, p->tnode, p->trun, p->tfirst, p->rowptr_n, nullptr,
                                p->tslot_ptr, p->tust, p->tslot);
+    }
+    // two-pass lists: per node-level slot its tile partials, per node its tile entries
+    {
+        p->n_tnodes = n_tn;
+        int64_t n_slots = 0;
+        FEM_HIP_TRY(hipMemcpyAsync(&n_slots, p->tslot_ptr + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        FEM_HIP_TRY(hipStreamSynchronize(s));
+        p->n_tslots = n_slots;
+        int32_t *keys = nullptr;
+        FEM_TRY(tmp.get(&keys, n_slots));
+        if (packed)
+            hipLaunchKernelGGL(k_tslot_keys<true>, dim3((unsigned)nt), dim3(kTT), 0, s, p->tnode_ptr,
+                               p->tnode, p->tslot_ptr, p->tslot, p->rowptr_n, keys);
+        else
+            hipLaunchKernelGGL(k_tslot_keys<false>, dim3((unsigned)nt), dim3(kTT), 0, s, p->tnode_ptr,
+                               p->tnode, p->tslot_ptr, p->tslot, p->rowptr_n, keys);
+        FEM_TRY(build_lists(p, tmp, keys, n_slots, p->nnz_nodes, &p->pslot_ptr, &p->pslot_idx, s));
+        FEM_TRY(build_lists(p, tmp, p->tnode, n_tn, N, &p->pnode_ptr, &p->pnode_idx, s));
     }
     FEM_TRY(pattern_alloc(p, (void **)&p->esub, sizeof(uint8_t) * E));
     FEM_TRY(pattern_alloc(p, (void **)&p->tile_nsub, sizeof(int32_t) * nt));

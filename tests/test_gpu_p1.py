@@ -432,3 +432,66 @@ def test_locality_order_and_input_order_agree(name):
             els = np.nonzero(col == c)[0]
             nodes = m.conn[:, els].ravel()
             assert np.unique(nodes).size == nodes.size, (io, c)
+
+
+@pytest.mark.parametrize("name", ["tri32", "tet12"])
+def test_two_pass_parity_and_reproducibility(name):
+    """Two-pass deterministic scatter: forward and adjoint match the oracle, and repeated
+    calls and a second pattern build give identical bits."""
+    m = MESHES[name]()
+    F = fem()
+    d = _dev(m)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=31)
+    form = F.Form("helmholtz", "sinprod")
+    rp, ci = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
+    G, g = meshgen.upstream_grads(int(rp[-1]), m.n_nodes, seed=31)
+    dk, adk, dx, adx = oracle.backward_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci, G, g)
+    kap = torch.from_numpy(kappa).cuda()
+    Gt, gt = torch.from_numpy(G).cuda(), torch.from_numpy(g).cuda()
+    outs = []
+    for build in range(2):
+        pat = F.Pattern(d)
+        for _ in range(2):
+            v, r = F.assemble(pat, d, form, kap, scatter="two-pass")
+            gk, gx = F.assemble_backward(pat, d, form, kap, Gt, gt, scatter="two-pass")
+            outs.append([_np(t).tobytes() for t in (v, r, gk, gx)])
+        assert scaled_close(_np(v), ov, oav, RTOL)[0]
+        assert scaled_close(_np(r), orhs, oar, RTOL)[0]
+        assert scaled_close(_np(gk)[0], dk, adk, RTOL)[0]
+        assert scaled_close(_np(gx), dx, adx, RTOL)[0]
+        # accumulate adds onto the buffers
+        v2, r2 = v.clone(), r.clone()
+        F.assemble(pat, d, form, kap, values=v2, rhs=r2, scatter="two-pass", accumulate=True)
+        np.testing.assert_allclose(_np(v2), 2 * _np(v), rtol=1e-14, atol=1e-14 * np.abs(_np(v)).max())
+        pat.close()
+    assert all(o == outs[0] for o in outs)
+
+
+def test_two_pass_full_size():
+    m, kappa, rp, ci, (ov, orhs, oav, oar) = c1()
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    form = F.Form("helmholtz", "sinprod", reaction=1.0)
+    v, r = F.assemble(pat, d, form, torch.from_numpy(kappa[None]).cuda(), scatter="two-pass")
+    ok, worst = scaled_close(_np(v), ov, oav, RTOL)
+    assert ok, worst
+    ok, worst = scaled_close(_np(r), orhs, oar, RTOL)
+    assert ok, worst
+
+
+def test_two_pass_rejects_coloured_combination():
+    F = fem()
+    m = MESHES["tet2"]()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    from paper_1802_03433_amd import _lib as L
+    import ctypes
+    kap = torch.ones(1, m.n_elems, dtype=torch.float64, device="cuda")
+    v = torch.empty(pat.nnz, dtype=torch.float64, device="cuda")
+    ms, fs = d.cstruct(), F.Form("helmholtz").cstruct()
+    rc = L.lib.fem_assemble(pat.handle, ctypes.byref(ms), ctypes.byref(fs), ctypes.c_void_p(kap.data_ptr()),
+                            ctypes.c_void_p(v.data_ptr()), None, L.SCATTER_TWO_PASS | L.SCATTER_COLOURED,
+                            None)
+    assert rc == -1

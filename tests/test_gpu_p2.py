@@ -345,3 +345,39 @@ def test_p2_backward_full_size_sampled():
         sub, coef[0, around], coef[1, around], "const", BF, rp, ci, G, g)
     ok, worst = scaled_close(gx[:, nodes], dx[:, nodes], adx[:, nodes], RTOL)
     assert ok, worst
+
+
+@pytest.mark.parametrize("n", [2, 5])
+def test_p2_two_pass_parity_and_reproducibility(n):
+    m, F, d, pat, coef, G, g = _bwd_case(n, 60 + n)
+    form = F.Form("elasticity", "const", load_const=BF)
+    c, Gt, gt = (torch.from_numpy(a).cuda() for a in (coef, G, g))
+    rp, ci = oracle.pattern(10, 3, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p2_elasticity(m, coef[0], coef[1], "const", BF, rp, ci)
+    dl, adl, dm, adm, dx, adx = oracle.backward_p2_elasticity(m, coef[0], coef[1], "const", BF,
+                                                              rp, ci, G, g)
+    outs = []
+    for _ in range(2):
+        v, r = F.assemble(pat, d, form, c, scatter="two-pass")
+        gc, gx = F.assemble_backward(pat, d, form, c, Gt, gt, scatter="two-pass")
+        outs.append([_np(t).tobytes() for t in (v, r, gc, gx)])
+    assert outs[0] == outs[1]
+    assert scaled_close(_np(v), ov, oav, RTOL)[0]
+    assert scaled_close(_np(r), orhs, oar, RTOL)[0]
+    assert scaled_close(_np(gc)[0], dl, adl, RTOL)[0]
+    assert scaled_close(_np(gc)[1], dm, adm, RTOL)[0]
+    ok, worst = scaled_close(_np(gx), dx, adx, RTOL)
+    assert ok, worst
+
+
+def test_p2_two_pass_full_size():
+    m, coef, rp, ci, (ov, orhs, oav, oar) = c2()
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d, ncomp=3)
+    form = F.Form("elasticity", "const", load_const=BF)
+    v, r = F.assemble(pat, d, form, torch.from_numpy(coef).cuda(), scatter="two-pass")
+    ok, worst = scaled_close(_np(v), ov, oav, RTOL)
+    assert ok, worst
+    ok, worst = scaled_close(_np(r), orhs, oar, RTOL)
+    assert ok, worst
