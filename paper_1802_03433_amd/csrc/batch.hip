@@ -334,8 +334,7 @@ int fem_assemble_batch(fem_batch *b, const fem_mesh *meshes, const fem_form *for
     if (!(flags & FEM_ACCUMULATE)) {
         // the coloured tile scatter stores on its first write of every slot and node row
         if (!coloured) {
-            FEM_TRY(fill_zero_f64(values, nnz, s));
-            if (rhs) FEM_TRY(fill_zero_f64(rhs, rows, s));
+            FEM_TRY(fill_zero2_f64(values, nnz, rhs, rows, s));
         } else if (rhs) {
             // rows no tile writes first: nodes in no element, meshes without a load
             for (int64_t k = 0; k < b->n_meshes; ++k)

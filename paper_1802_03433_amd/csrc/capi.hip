@@ -270,9 +270,9 @@ int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *for
         // slot, so only the RHS of nodes in no element needs clearing; the two-pass
         // scatter writes every slot and row
         const bool two_pass = (flags & FEM_SCATTER_TWO_PASS) != 0;
-        if (!(tiles && (coloured || two_pass))) FEM_TRY(fill_zero_f64(values, p->nnz, s));
-        if (rhs_ok && !two_pass && (!(tiles && coloured) || p->has_isolated_nodes))
-            FEM_TRY(fill_zero_f64(rhs_ok, p->n_rows, s));
+        const bool zv = !(tiles && (coloured || two_pass));
+        const bool zr = rhs_ok && !two_pass && (!(tiles && coloured) || p->has_isolated_nodes);
+        FEM_TRY(fill_zero2_f64(zv ? values : nullptr, p->nnz, zr ? rhs_ok : nullptr, p->n_rows, s));
     }
     if (elast) return p2_tile_forward(p, mesh, form, coef, values, rhs_ok, flags, s);
     if (tiles) return p1_tile_forward(p, mesh, form, coef, values, rhs_ok, flags, s);

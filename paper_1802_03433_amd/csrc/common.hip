@@ -73,6 +73,38 @@ int fill_zero_f64(double *p, int64_t n, hipStream_t s)
     return FEM_OK;
 }
 
+// Two ranges in one launch: 16-byte stores, one 8-byte store at an unaligned head or an
+// odd tail
+__global__ void k_fill_zero2_f64(double *__restrict__ a, int64_t na, double *__restrict__ b, int64_t nb)
+{
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int r = 0; r < 2; ++r) {
+        double *p = r ? b : a;
+        const int64_t n = r ? nb : na;
+        if (n <= 0) continue;
+        const int64_t h = ((uintptr_t)p & 15u) ? 1 : 0;
+        if (h && t0 == 0) p[0] = 0.0;
+        double *q = p + h;
+        const int64_t m = n - h, pairs = m / 2;
+        for (int64_t i = t0; i < pairs; i += stride) reinterpret_cast<double2 *>(q)[i] = make_double2(0.0, 0.0);
+        if ((m & 1) && t0 == 0) q[m - 1] = 0.0;
+    }
+}
+
+int fill_zero2_f64(double *a, int64_t na, double *b, int64_t nb, hipStream_t s)
+{
+    if (!a) na = 0;
+    if (!b) nb = 0;
+    if (na <= 0 && nb <= 0) return FEM_OK;
+    const int64_t pairs = (std::max(na, nb) + 1) / 2;
+    const int threads = 256;
+    const int64_t blocks = std::min<int64_t>(8192, std::max<int64_t>(1, (pairs + threads - 1) / threads));
+    hipLaunchKernelGGL(k_fill_zero2_f64, dim3((unsigned)blocks), dim3(threads), 0, s, a, na, b, nb);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
 __global__ void k_fill_zero_i32(int32_t *__restrict__ p, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -226,6 +226,8 @@ int scan_counts_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
 
 // fill kernels (graph-capture safe alternative to hipMemsetAsync)
 int fill_zero_f64(double *p, int64_t n, hipStream_t s);
+// zeroes a[0, na) and b[0, nb) in one launch (a NULL pointer or a count <= 0 skips a range)
+int fill_zero2_f64(double *a, int64_t na, double *b, int64_t nb, hipStream_t s);
 int fill_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 
 // pattern construction (pattern.hip)

@@ -194,24 +194,14 @@ __device__ __forceinline__ void qpoint(const Elem<D> &g, int q, double *xq)
     }
 }
 
-// One element of a staged tile (Alg. 1's per-element steps): vertex coordinates from the
-// tile's LDS, geometry, the element matrix A (stiffness + mass, exact for affine
-// elements), the tile-local slot index of each entry, and the load vector by the rule.
+// Element matrix A (stiffness + mass, exact for affine elements) and load vector by the
+// rule, from the element's vertex coordinates (Alg. 1's per-element steps)
 template <int D, int LOAD>
-__device__ __forceinline__ void p1_element(const TileArgs &a, const Lds<D> &L, uint64_t en,
-                                           const uint32_t pr[D + 1], double kap,
-                                           double A[D + 1][D + 1], double bv[D + 1], int ki[D + 1],
-                                           int li[D + 1][D + 1])
+__device__ __forceinline__ void p1_local(const TileArgs &a, Elem<D> &g, double kap,
+                                         double A[D + 1][D + 1], double bv[D + 1])
 {
     constexpr int NP = D + 1;
     using R = quad::P1Rule<D>;
-    Elem<D> g;
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        ki[k] = (int)((en >> (16 * k)) & 0xffffu);
-#pragma unroll
-        for (int d = 0; d < D; ++d) g.x[k][d] = L.xs[d * a.nmax + ki[k]];
-    }
     elem_geometry<D>(g);
     const double kv = kap * g.vol, cv = a.c * g.vol;
 #pragma unroll
@@ -224,16 +214,6 @@ __device__ __forceinline__ void p1_element(const TileArgs &a, const Lds<D> &L, u
             A[i][j] = kv * s + cv * quad::p1_mass<D>(i, j);
             A[j][i] = A[i][j];
         }
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        const uint64_t r = L.rb[ki[i]];
-        const int base = L.ust[ki[i]];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            const int p = (int)((pr[i] >> (8 * j)) & 0xffu);
-            li[i][j] = base + __popcll(r & ((1ull << p) - 1ull));
-        }
-    }
 #pragma unroll
     for (int i = 0; i < NP; ++i) bv[i] = 0.0;
     if constexpr (LOAD != FEM_LOAD_NONE) {
@@ -252,6 +232,35 @@ __device__ __forceinline__ void p1_element(const TileArgs &a, const Lds<D> &L, u
             const double wf = g.vol * R::w(q) * f;
 #pragma unroll
             for (int i = 0; i < NP; ++i) bv[i] += wf * R::lam(q, i);
+        }
+    }
+}
+
+// One element of a staged tile: vertex coordinates from the tile's LDS, the local matrix
+// and load vector, and the tile-local slot index of each entry.
+template <int D, int LOAD>
+__device__ __forceinline__ void p1_element(const TileArgs &a, const double *xs, const uint64_t *rb,
+                                           const int32_t *ust, uint64_t en, const uint32_t pr[D + 1],
+                                           double kap, double A[D + 1][D + 1], double bv[D + 1],
+                                           int ki[D + 1], int li[D + 1][D + 1])
+{
+    constexpr int NP = D + 1;
+    Elem<D> g;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        ki[k] = (int)((en >> (16 * k)) & 0xffffu);
+#pragma unroll
+        for (int d = 0; d < D; ++d) g.x[k][d] = xs[d * a.nmax + ki[k]];
+    }
+    p1_local<D, LOAD>(a, g, kap, A, bv);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const uint64_t r = rb[ki[i]];
+        const int base = ust[ki[i]];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int p = (int)((pr[i] >> (8 * j)) & 0xffu);
+            li[i][j] = base + __popcll(r & ((1ull << p) - 1ull));
         }
     }
 }
@@ -284,7 +293,7 @@ __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
 
     double A[NP][NP], bv[NP];
     int ki[NP], li[NP][NP];
-    if (active) p1_element<D, LOAD>(a, L, en, pr, kap, A, bv, ki, li);
+    if (active) p1_element<D, LOAD>(a, L.xs, L.rb, L.ust, en, pr, kap, A, bv, ki, li);
     if (MODE == kAtomic) {
         if (active) {
 #pragma unroll

@@ -248,9 +248,11 @@ def test_ordered_single_launch_equals_colour_launches(name):
 
 
 @pytest.mark.parametrize("scatter", ["atomic", "coloured"])
-def test_accumulate_adds(scatter):
-    """FEM_ACCUMULATE adds the assembled system onto what the buffers hold."""
-    m = MESHES["tet12"]()
+@pytest.mark.parametrize("name", ["tri32", "tet12"])
+def test_accumulate_adds(name, scatter):
+    """FEM_ACCUMULATE adds the assembled system onto what the buffers hold (the atomic
+    scatter seeds the entries of one tile alone with the buffer's values)."""
+    m = MESHES[name]()
     F = fem()
     d = _dev(m)
     pat = F.Pattern(d)
