@@ -12,6 +12,7 @@
 //   C  one global update per distinct slot and node, coalesced (the slot list is sorted):
 //      device-scope FP64 atomics, or -- colour by colour -- plain stores (first writer of
 //      a slot) and read-modify-writes.
+#include <cfloat>
 #include <cstring>
 
 #include "fem_internal.h"
@@ -55,6 +56,9 @@ struct TileArgs {
     bool accumulate;
 };
 
+// exponent mark of a slot without nonzero contributions (deterministic forward)
+constexpr int kNoExp = -4000;
+
 // LDS carve-up shared by the forward and adjoint kernels
 template <int D>
 struct Lds {
@@ -67,6 +71,7 @@ struct Lds {
     int32_t *us;   // [smax]     slot list (~slot marks a first writer)
     int32_t *nd;   // [nmax]     node ids
     uint8_t *nf;   // [nmax]     node first-writer flags
+    int32_t *xe;   // [smax+nmax] deterministic forward: per-slot, per-node sum exponents
     __device__ Lds(unsigned char *base, int nmax, int smax)
     {
         xs = (double *)base;
@@ -77,7 +82,8 @@ struct Lds {
         ust = (int32_t *)(rb + nmax);
         us = ust + nmax;
         nd = us + smax;
-        nf = (uint8_t *)(nd + nmax);
+        xe = nd + nmax;
+        nf = (uint8_t *)(xe + smax + nmax);
     }
 };
 
@@ -85,7 +91,7 @@ template <int D>
 size_t lds_bytes(int nmax, int smax)
 {
     return sizeof(double) * (size_t)(2 * D * nmax + smax + nmax) + sizeof(uint64_t) * nmax +
-           sizeof(int32_t) * (size_t)(nmax + smax + nmax) + (size_t)nmax + 16;
+           sizeof(int32_t) * (size_t)(nmax + smax + nmax + smax + nmax) + (size_t)nmax + 16;
 }
 
 // Phase A: the tile's nodes (coordinates, row masks, run offsets) and its distinct-slot
@@ -94,7 +100,7 @@ size_t lds_bytes(int nmax, int smax)
 // the upstream gradient of every slot.
 template <int D>
 __device__ int stage_tile(const TileArgs &a, Lds<D> &L, int64_t tile, int nn, bool slot_first,
-                          bool gather_grad)
+                          bool gather_grad, bool fixed_point = false)
 {
     const int n0 = a.tnode_ptr[tile];
     const int64_t s0 = a.tslot_ptr[tile];
@@ -111,12 +117,14 @@ __device__ int stage_tile(const TileArgs &a, Lds<D> &L, int64_t tile, int nn, bo
             L.nacc[d * a.nmax + k] = 0.0;
         }
         if (gather_grad) L.gr[k] = a.grhs ? a.grhs[n] : 0.0;
+        if (fixed_point) L.xe[a.smax + k] = kNoExp;
     }
     for (int u = threadIdx.x; u < ns; u += blockDim.x) {
         const int32_t sl = a.tslot[s0 + u];
         const int32_t plain = sl < 0 ? ~sl : sl;
         L.us[u] = slot_first ? sl : plain;
         L.sacc[u] = (gather_grad && a.gvalues) ? a.gvalues[plain] : 0.0;
+        if (fixed_point) L.xe[u] = kNoExp;
     }
     __syncthreads();
     return ns;
@@ -265,6 +273,27 @@ __device__ __forceinline__ void p1_element(const TileArgs &a, const double *xs, 
     }
 }
 
+// ---- order-independent sums inside a tile (deterministic scatter modes) ----------------
+// Every contribution v to a slot (node row) of the tile is rounded to a multiple of 2^-s,
+// with s = 51 - e for the slot's largest nonzero contribution M < 2^e (an LDS max over the
+// binary exponents first), so |v 2^s| < 2^51 and up to 1024 terms add exactly in int64.
+// Integer adds commute: the LDS sums do not depend on the order the atomics run in.
+// Error: at most 2^(e-52) <= 2^-51 M per term, and one rounding converting back.
+__device__ __forceinline__ int fx_exp(double v)  // |v| < 2^e, v finite and nonzero
+{
+    int e;
+    (void)frexp(v, &e);
+    return e;
+}
+
+// round(v 2^s) for |v 2^s| < 2^51: adding 1.5 * 2^52 leaves the integer in the low
+// mantissa bits (the scaling by 2^s is exact)
+__device__ __forceinline__ unsigned long long fx_round(double v, int s)
+{
+    const double magic = 6755399441055744.0;
+    return (unsigned long long)(__double_as_longlong(ldexp(v, s) + magic) - 0x4338000000000000ll);
+}
+
 template <int D, int LOAD, int MODE>
 __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
 {
@@ -289,7 +318,7 @@ __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
         kap = a.kappa[a.telem ? a.telem[e] : e];
         if (MODE != kAtomic) sc = a.esub[e];
     }
-    const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false);
+    const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false, MODE != kAtomic);
 
     double A[NP][NP], bv[NP];
     int ki[NP], li[NP][NP];
@@ -304,17 +333,63 @@ __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
             }
         }
     } else {
-        const int nsub = a.tile_nsub[tile];
-        for (int s = 0; s < nsub; ++s) {
-            if (active && sc == s) {
+        // deterministic: fixed-point LDS sums; a tile with a non-finite contribution adds
+        // in its intra-tile colour phases instead
+        int32_t *xs_e = L.xe, *xn_e = L.xe + a.smax;
+        bool bad = false;
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    const double v = A[i][j];
+                    bad |= !(fabs(v) <= DBL_MAX);
+                    if (v != 0.0) atomicMax(&xs_e[li[i][j]], fx_exp(v));
+                }
+                if (LOAD != FEM_LOAD_NONE) {
+                    const double v = bv[i];
+                    bad |= !(fabs(v) <= DBL_MAX);
+                    if (v != 0.0) atomicMax(&xn_e[ki[i]], fx_exp(v));
+                }
+            }
+        }
+        bad = __syncthreads_or(bad) != 0;
+        if (!bad) {
+            unsigned long long *ia = reinterpret_cast<unsigned long long *>(L.sacc);
+            unsigned long long *ib = reinterpret_cast<unsigned long long *>(L.nacc);
+            if (active) {
 #pragma unroll
                 for (int i = 0; i < NP; ++i) {
 #pragma unroll
-                    for (int j = 0; j < NP; ++j) L.sacc[li[i][j]] += A[i][j];
-                    if (LOAD != FEM_LOAD_NONE) L.nacc[ki[i]] += bv[i];
+                    for (int j = 0; j < NP; ++j) {
+                        const int k = li[i][j];
+                        atomicAdd(&ia[k], fx_round(A[i][j], 51 - xs_e[k]));
+                    }
+                    if (LOAD != FEM_LOAD_NONE) {
+                        const int k = ki[i];
+                        atomicAdd(&ib[k], fx_round(bv[i], 51 - xn_e[k]));
+                    }
                 }
             }
             __syncthreads();
+            for (int u = threadIdx.x; u < ns; u += blockDim.x)
+                L.sacc[u] = ldexp((double)(long long)ia[u], xs_e[u] - 51);
+            if (LOAD != FEM_LOAD_NONE)
+                for (int k = threadIdx.x; k < nn; k += blockDim.x)
+                    L.nacc[k] = ldexp((double)(long long)ib[k], xn_e[k] - 51);
+        } else {
+            const int nsub = a.tile_nsub[tile];
+            for (int s = 0; s < nsub; ++s) {
+                if (active && sc == s) {
+#pragma unroll
+                    for (int i = 0; i < NP; ++i) {
+#pragma unroll
+                        for (int j = 0; j < NP; ++j) L.sacc[li[i][j]] += A[i][j];
+                        if (LOAD != FEM_LOAD_NONE) L.nacc[ki[i]] += bv[i];
+                    }
+                }
+                __syncthreads();
+            }
         }
     }
     __syncthreads();

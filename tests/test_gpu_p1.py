@@ -228,6 +228,33 @@ def test_coloured_is_bitwise_reproducible():
     assert all(o == outs[0] for o in outs)
 
 
+def test_deterministic_tile_with_infinite_coefficient():
+    """A tile whose contributions are not all finite takes the intra-tile colour phases
+    instead of the fixed-point sums: the same non-finite entries as the atomic scatter,
+    the finite entries within tolerance, and still one result for both coloured forms."""
+    m = MESHES["tet12"]()
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kap_np = meshgen.coefficients(m.n_elems, "helmholtz", seed=21)
+    kap_np[0, [5, 4000]] = [np.inf, -np.inf]
+    kap = torch.from_numpy(kap_np).cuda()
+    form = F.Form("helmholtz", "sinprod")
+    outs = {sc: [_np(t) for t in F.assemble(pat, d, form, kap, scatter=sc)]
+            for sc in ("atomic", "coloured", "coloured-launches")}
+    va, ra = outs["atomic"]
+    for sc in ("coloured", "coloured-launches"):
+        v, r = outs[sc]
+        np.testing.assert_array_equal(np.isnan(v), np.isnan(va))
+        np.testing.assert_array_equal(np.isposinf(v), np.isposinf(va))
+        np.testing.assert_array_equal(np.isneginf(v), np.isneginf(va))
+        fin = np.isfinite(va)
+        assert 0 < fin.sum() < fin.size
+        np.testing.assert_allclose(v[fin], va[fin], rtol=1e-12, atol=1e-12 * np.abs(va[fin]).max())
+        np.testing.assert_allclose(r, ra, rtol=1e-12, atol=1e-12 * np.abs(ra).max())
+    assert outs["coloured"][0].tobytes() == outs["coloured-launches"][0].tobytes()
+
+
 @pytest.mark.parametrize("name", ["tri32", "tet12"])
 def test_ordered_single_launch_equals_colour_launches(name):
     """The single-launch coloured scatter applies every slot's contributions in the same
