@@ -398,6 +398,13 @@ def main():
         extra["bwd_ms"] = bwd_ms
         extra["bwd_over_fwd"] = bwd_ms / ms_per_step
         extra["bwd_alg_GBps"] = _alg_bytes_bwd(E, N, nnz) / (bwd_ms * 1e-3) / 1e9
+        for sc in ("coloured", "two-pass"):
+            def bwd_det():
+                fem.assemble_backward(pat, dm, form, kappa, G, g, grad_coef=gk, grad_coords=gx,
+                                      scatter=sc)
+
+            bwd_det()
+            extra[f"bwd_{sc.replace('-', '_')}_ms"] = _time_calls(torch, bwd_det, args.steps)
     if not args.no_extra and "p2" in sections:
         extra["p2_elasticity"] = _bench_p2(torch, fem, meshgen, dev, max(5, args.steps // 3))
         torch.cuda.empty_cache()

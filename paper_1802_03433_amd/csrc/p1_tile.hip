@@ -71,7 +71,8 @@ struct Lds {
     int32_t *us;   // [smax]     slot list (~slot marks a first writer)
     int32_t *nd;   // [nmax]     node ids
     uint8_t *nf;   // [nmax]     node first-writer flags
-    int32_t *xe;   // [smax+nmax] deterministic forward: per-slot, per-node sum exponents
+    int32_t *xe;   // [smax+D*nmax] deterministic sums: exponents per slot and node row
+                   // (forward), per node and axis (adjoint)
     __device__ Lds(unsigned char *base, int nmax, int smax)
     {
         xs = (double *)base;
@@ -83,7 +84,7 @@ struct Lds {
         us = ust + nmax;
         nd = us + smax;
         xe = nd + nmax;
-        nf = (uint8_t *)(xe + smax + nmax);
+        nf = (uint8_t *)(xe + smax + D * nmax);
     }
 };
 
@@ -91,16 +92,18 @@ template <int D>
 size_t lds_bytes(int nmax, int smax)
 {
     return sizeof(double) * (size_t)(2 * D * nmax + smax + nmax) + sizeof(uint64_t) * nmax +
-           sizeof(int32_t) * (size_t)(nmax + smax + nmax + smax + nmax) + (size_t)nmax + 16;
+           sizeof(int32_t) * (size_t)(nmax + smax + nmax + smax + D * nmax) + (size_t)nmax + 16;
 }
 
 // Phase A: the tile's nodes (coordinates, row masks, run offsets) and its distinct-slot
 // list, both precomputed in the plan and loaded coalesced.  Returns the number of distinct
 // slots.  slot_first keeps the first-writer marks (~slot) of the list; the adjoint gathers
 // the upstream gradient of every slot.
+// `fixed_point` marks the exponents of the deterministic sums empty: 1 the forward's slots
+// and node rows, 2 the adjoint's node axes.
 template <int D>
 __device__ int stage_tile(const TileArgs &a, Lds<D> &L, int64_t tile, int nn, bool slot_first,
-                          bool gather_grad, bool fixed_point = false)
+                          bool gather_grad, int fixed_point = 0)
 {
     const int n0 = a.tnode_ptr[tile];
     const int64_t s0 = a.tslot_ptr[tile];
@@ -117,14 +120,17 @@ __device__ int stage_tile(const TileArgs &a, Lds<D> &L, int64_t tile, int nn, bo
             L.nacc[d * a.nmax + k] = 0.0;
         }
         if (gather_grad) L.gr[k] = a.grhs ? a.grhs[n] : 0.0;
-        if (fixed_point) L.xe[a.smax + k] = kNoExp;
+        if (fixed_point == 1) L.xe[a.smax + k] = kNoExp;
+        if (fixed_point == 2)
+#pragma unroll
+            for (int d = 0; d < D; ++d) L.xe[d * a.nmax + k] = kNoExp;
     }
     for (int u = threadIdx.x; u < ns; u += blockDim.x) {
         const int32_t sl = a.tslot[s0 + u];
         const int32_t plain = sl < 0 ? ~sl : sl;
         L.us[u] = slot_first ? sl : plain;
         L.sacc[u] = (gather_grad && a.gvalues) ? a.gvalues[plain] : 0.0;
-        if (fixed_point) L.xe[u] = kNoExp;
+        if (fixed_point == 1) L.xe[u] = kNoExp;
     }
     __syncthreads();
     return ns;
@@ -318,7 +324,7 @@ __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
         kap = a.kappa[a.telem ? a.telem[e] : e];
         if (MODE != kAtomic) sc = a.esub[e];
     }
-    const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false, MODE != kAtomic);
+    const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false, MODE != kAtomic ? 1 : 0);
 
     double A[NP][NP], bv[NP];
     int ki[NP], li[NP][NP];
@@ -460,7 +466,7 @@ __device__ __forceinline__ void p1_bwd_tile(const TileArgs &a, int64_t tile)
         kap = a.kappa[eu];
         if (MODE != kAtomic) sc = a.esub[e];
     }
-    stage_tile<D>(a, L, tile, nn, false, true);
+    stage_tile<D>(a, L, tile, nn, false, true, (MODE != kAtomic && a.gcoords) ? 2 : 0);
 
     double xbar[NP][D];
     int ki[NP];
@@ -578,15 +584,49 @@ __device__ __forceinline__ void p1_bwd_tile(const TileArgs &a, int64_t tile)
                 for (int d = 0; d < D; ++d) atomicAdd(&L.nacc[d * a.nmax + ki[k]], xbar[k][d]);
         }
     } else {
-        const int nsub = a.tile_nsub[tile];
-        for (int s = 0; s < nsub; ++s) {
-            if (active && sc == s) {
+        // deterministic: fixed-point LDS sums per node and axis (colour phases for a tile
+        // with a non-finite contribution)
+        bool bad = false;
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const double v = xbar[k][d];
+                    bad |= !(fabs(v) <= DBL_MAX);
+                    if (v != 0.0) atomicMax(&L.xe[d * a.nmax + ki[k]], fx_exp(v));
+                }
+        }
+        bad = __syncthreads_or(bad) != 0;
+        if (!bad) {
+            unsigned long long *ix = reinterpret_cast<unsigned long long *>(L.nacc);
+            if (active) {
 #pragma unroll
                 for (int k = 0; k < NP; ++k)
 #pragma unroll
-                    for (int d = 0; d < D; ++d) L.nacc[d * a.nmax + ki[k]] += xbar[k][d];
+                    for (int d = 0; d < D; ++d) {
+                        const int t = d * a.nmax + ki[k];
+                        atomicAdd(&ix[t], fx_round(xbar[k][d], 51 - L.xe[t]));
+                    }
             }
             __syncthreads();
+            for (int k = threadIdx.x; k < nn; k += blockDim.x)
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int t = d * a.nmax + k;
+                    L.nacc[t] = ldexp((double)(long long)ix[t], L.xe[t] - 51);
+                }
+        } else {
+            const int nsub = a.tile_nsub[tile];
+            for (int s = 0; s < nsub; ++s) {
+                if (active && sc == s) {
+#pragma unroll
+                    for (int k = 0; k < NP; ++k)
+#pragma unroll
+                        for (int d = 0; d < D; ++d) L.nacc[d * a.nmax + ki[k]] += xbar[k][d];
+                }
+                __syncthreads();
+            }
         }
     }
     __syncthreads();
