@@ -323,6 +323,13 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
             lm = a.lam[eu];
             mm = a.mu[eu];
         }
+        // the lane's entries of P: rows q = 4 ks + hi, columns lo and 16 + lo (every MFMA
+        // operand of the four output tiles is one of these eight)
+        double pv[4][2];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) pv[ks][cb] = has ? sv * pvalp(L.R, 4 * ks + hi, 16 * cb + lo, inv) : 0.0;
         // K blocks of this wavefront's element: in strip h, lane < 50 takes the node pair
         // (5h + lane / 10, lane % 10)
         double kb[2][9];
@@ -332,14 +339,12 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
             if (has) {
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
-                    const int rc = 16 * h + lo, cc = 16 * cb + lo;
                     if constexpr (F32) {
                         f4_t g = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                         for (int ks = 0; ks < 4; ++ks) {
-                            const int q = 4 * ks + hi;
-                            const float av = (float)(sv * pvalp(L.R, q, rc, inv));
-                            const float bv = (float)(sv * pvalp(L.R, q, cc, inv));
+                            const float av = (float)pv[ks][h];
+                            const float bv = (float)pv[ks][cb];
                             g = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, g, 0, 0, 0);
                         }
                         // f32 16x16x4 output layout: register r of lane l holds row 4 (l / 16) + r
@@ -348,12 +353,8 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
                     } else {
                         d4_t g = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                        for (int ks = 0; ks < 4; ++ks) {
-                            const int q = 4 * ks + hi;
-                            const double av = sv * pvalp(L.R, q, rc, inv);
-                            const double bv = sv * pvalp(L.R, q, cc, inv);
-                            g = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, g, 0, 0, 0);
-                        }
+                        for (int ks = 0; ks < 4; ++ks)
+                            g = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[ks][h], pv[ks][cb], g, 0, 0, 0);
                         // f64 16x16x4 output layout (measured on gfx950): register r of lane l
                         // holds row (l / 16) + 4 r, column l % 16
 #pragma unroll
