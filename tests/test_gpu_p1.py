@@ -4,6 +4,8 @@ the scaled rule |gpu - oracle| <= 1e-12 * max(|oracle|, sum |element contributio
 plus the normwise rule ||gpu - oracle||_inf <= 1e-12 ||oracle||_inf.
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -253,6 +255,44 @@ def test_deterministic_tile_with_infinite_coefficient():
         np.testing.assert_allclose(v[fin], va[fin], rtol=1e-12, atol=1e-12 * np.abs(va[fin]).max())
         np.testing.assert_allclose(r, ra, rtol=1e-12, atol=1e-12 * np.abs(ra).max())
     assert outs["coloured"][0].tobytes() == outs["coloured-launches"][0].tobytes()
+
+
+@pytest.mark.parametrize("scale", [1e-100, 1e100])
+@pytest.mark.parametrize("scatter", ["atomic", "coloured", "two-pass"])
+def test_extreme_scales(scale, scatter):
+    """Entries near both ends of the FP64 range: the load vector ~ |T| ~ 1e-305 and 1e296,
+    the matrix ~ 1e-101 and 1e99.  The fixed-point tile sums of the deterministic modes
+    take their scale per slot from the contributions' exponents and keep the oracle's
+    accuracy, like the atomic scatter, in the forward and the adjoint.  The reaction
+    coefficient is scale^-2 so that mass and stiffness stay comparable: stiffness scales
+    as h and mass as h^3, so with c = 1 the rounding residue of an exactly cancelling
+    stiffness entry would dwarf a mass-only entry at h ~ 1e-100."""
+    m0 = MESHES["tet12"]()
+    m = dataclasses.replace(m0, coords=m0.coords * scale)
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=8)
+    c = scale ** -2
+    form = F.Form("helmholtz", "const", reaction=c, load_const=(0.7,))
+    kt = torch.from_numpy(kappa).cuda()
+    v, r = F.assemble(pat, d, form, kt, scatter=scatter)
+    rp, ci = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], c, "const", [0.7], rp, ci)
+    G, g = meshgen.upstream_grads(pat.nnz, pat.n_rows, seed=8)
+    gk, gx = F.assemble_backward(pat, d, form, kt, torch.from_numpy(G).cuda(),
+                                 torch.from_numpy(g).cuda(), scatter=scatter)
+    dk, adk, dx, adx = oracle.backward_p1(m, kappa[0], c, "const", [0.7], rp, ci, G, g)
+    checks = [("values", _np(v), ov, oav), ("rhs", _np(r), orhs, oar),
+              ("dkappa", _np(gk).ravel(), dk, adk)]
+    if scale > 1.0:  # the oracle's complex step (h = 1e-30) needs coordinates far above h
+        checks.append(("dcoords", _np(gx), dx, adx))
+    for what, got, ref, sc in checks:
+        ok, worst = scaled_close(got, ref, sc, RTOL)
+        if not ok:
+            got, ref, sc = (np.asarray(x, dtype=np.float64).ravel() for x in (got, ref, sc))
+            k = int(np.argmax(np.abs(got - ref) / np.maximum(np.maximum(np.abs(ref), sc), 1e-300)))
+            pytest.fail(f"{what}: worst {worst:.3g} at {k}: got {got[k]!r} ref {ref[k]!r} scale {sc[k]!r}")
 
 
 @pytest.mark.parametrize("name", ["tri32", "tet12"])
