@@ -1,6 +1,7 @@
 // Error state, device scans and fills shared by the library's kernels.
 #include <map>
 #include <mutex>
+#include <tuple>
 
 #include "fem_internal.h"
 
@@ -24,6 +25,25 @@ void ensure_lds_attr(const void *kernel, size_t lds)
         (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         d = lds;
     }
+}
+
+int64_t resident_blocks(const void *kernel, int threads, size_t lds)
+{
+    using Key = std::tuple<int, const void *, int, size_t>;
+    static std::mutex mu;
+    static std::map<Key, int64_t> known;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = known.find(Key{dev, kernel, threads, lds});
+    if (it != known.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
+    const int64_t n = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
+    known[Key{dev, kernel, threads, lds}] = n;
+    return n;
 }
 
 int pattern_alloc(fem_pattern *p, void **ptr, size_t bytes)

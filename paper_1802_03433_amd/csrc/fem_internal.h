@@ -304,6 +304,9 @@ inline unsigned grid_for(int64_t n, int threads)
 // Dynamic LDS above 64 KB needs the kernel attribute; it is set once per kernel and size
 // (in practice outside any stream capture: the first call of a configuration sets it).
 void ensure_lds_attr(const void *kernel, size_t lds);
+// Workgroups of `kernel` (threads, dynamic LDS bytes) resident on the whole current device
+// at once: the occupancy per CU times the CU count, cached per device and configuration.
+int64_t resident_blocks(const void *kernel, int threads, size_t lds);
 template <class K>
 void ensure_lds(K kernel, size_t lds)
 {

@@ -284,19 +284,12 @@ __device__ __forceinline__ double pvalp(const double *R, int q, int c, const dou
     return r[0] * inv[0][a] + r[1] * inv[1][a] + r[2] * inv[2][a];
 }
 
+// Phase B of the forward: the tile's element matrices on the matrix cores, combined per
+// distinct node pair in LDS.
 template <int MODE, bool F32>
-__device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
+__device__ __forceinline__ void p2_elements(const P2Args &a, P2Lds &L, int64_t e0, int ne)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    P2Lds L(smem, a.nmax, a.smax, a.T, false);
     const int tid = threadIdx.x;
-    const int n0 = a.tnode_ptr[tile];
-    const int nn = a.tnode_ptr[tile + 1] - n0;
-    const int64_t e0 = tile * a.T;
-    const int ne = (int)min((int64_t)a.T, a.E - e0);
-
-    const int total = p2_stage(a, L, tile, n0, nn, e0, ne, false);
-
     // ---- elements: one per wavefront, four in flight ----
     // G is formed in two strips of 16 rows (tiles (h,0) and (h,1)); its columns are
     // node-padded (node i, component a -> 16 (i / 5) + 3 (i % 5) + a), so strip h holds
@@ -421,8 +414,13 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
         }
     }
     __syncthreads();
+}
 
-    // ---- one global update per distinct (pair, a, b) and per (node, a) ----
+// Phase C of the forward: one global update per distinct (pair, a, b) and per (node, a).
+template <int MODE>
+__device__ __forceinline__ void p2_global(const P2Args &a, P2Lds &L, int64_t tile, int nn, int total)
+{
+    const int tid = threadIdx.x;
     const int nvals = 9 * total;
     if (MODE == kOrdered) {
         wait_preds(a.pred_ptr, a.pred, a.flags, a.err, tile);
@@ -469,6 +467,20 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
             else *dst += v;
         }
     }
+}
+
+template <int MODE, bool F32>
+__device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    P2Lds L(smem, a.nmax, a.smax, a.T, false);
+    const int n0 = a.tnode_ptr[tile];
+    const int nn = a.tnode_ptr[tile + 1] - n0;
+    const int64_t e0 = tile * a.T;
+    const int ne = (int)min((int64_t)a.T, a.E - e0);
+    const int total = p2_stage(a, L, tile, n0, nn, e0, ne, false);
+    p2_elements<MODE, F32>(a, L, e0, ne);
+    p2_global<MODE>(a, L, tile, nn, total);
 }
 
 
@@ -686,6 +698,150 @@ __global__ __launch_bounds__(kP2Threads) __attribute__((amdgpu_waves_per_eu(3)))
     p2_bwd_tile<MODE>(a, (MODE == kAtomic || MODE == kTwoPass) ? i : a.tile_list[i]);
 }
 
+
+// ---- persistent forward, next tile's lists prefetched (atomic and two-pass) -------------
+// Every workgroup walks a share of one XCD's tiles.  After the element phase of a tile it
+// issues the loads of the next tile's node lists, pair codes, row positions and node
+// indices into registers, so their latency overlaps the global updates; staging the next
+// tile then waits for one level of dependent loads (coordinates, row offsets) instead of
+// three.  The prefetch follows the element phase because global loads complete in issue
+// order: the element loop's own loads would otherwise wait for it.  (Reading the
+// elements' node indices and coefficients from LDS instead, and prefetching before the
+// element phase, measured slower.)  Thread k holds node k and pairs k + 256 q, q < 4:
+// tiles of at most 8 elements, 256 nodes, 1024 pairs.
+constexpr int kP2PipeMaxPairs = 4;
+
+struct P2Meta {
+    int32_t n0, nn, total;
+    int64_t s0, e0;
+    int ne;
+};
+
+__device__ __forceinline__ P2Meta p2_meta(const P2Args &a, int64_t tile, bool valid)
+{
+    P2Meta m{0, 0, 0, 0, 0, 0};
+    if (valid) {
+        m.n0 = a.tnode_ptr[tile];
+        m.nn = a.tnode_ptr[tile + 1] - m.n0;
+        m.s0 = a.tslot_ptr[tile];
+        m.total = (int32_t)(a.tslot_ptr[tile + 1] - m.s0);
+        m.e0 = tile * a.T;
+        m.ne = (int)min((int64_t)a.T, a.E - m.e0);
+    }
+    return m;
+}
+
+struct P2Pre {
+    int32_t tn, ust, code[kP2PipeMaxPairs];
+    uint64_t rb0, rb1;
+    uint32_t pos, enw;
+};
+
+__device__ __forceinline__ void p2_prefetch(const P2Args &a, const P2Meta &m, P2Pre &pf)
+{
+    const int tid = threadIdx.x;
+    if (tid < m.nn) {
+        const int64_t k = m.n0 + tid;
+        pf.tn = a.tnode[k];
+        pf.rb0 = a.trun[2 * k];
+        pf.rb1 = a.trun[2 * k + 1];
+        pf.ust = a.tust[k];
+    }
+#pragma unroll
+    for (int q = 0; q < kP2PipeMaxPairs; ++q) {
+        const int u = tid + q * kP2Threads;
+        if (u < m.total) pf.code[q] = a.tslot[m.s0 + u];
+    }
+    // 100 position bytes and 10 uint16 node indices per element: whole 32-bit words
+    if (tid < m.ne * 25) pf.pos = reinterpret_cast<const uint32_t *>(a.epos + m.e0 * NPE * NPE)[tid];
+    if (tid < m.ne * 5) pf.enw = reinterpret_cast<const uint32_t *>(a.enode + m.e0 * NPE)[tid];
+}
+
+// Stage a prefetched tile: lists into LDS with the coordinates and row offsets of its
+// nodes, then the pair index of every (element, i, j).
+__device__ __forceinline__ void p2_commit(const P2Args &a, P2Lds &L, uint16_t *en, const P2Meta &m,
+                                          const P2Pre &pf)
+{
+    const int tid = threadIdx.x;
+    if (tid < m.nn) {
+        const int32_t n = pf.tn;
+        L.nd[tid] = n;
+        L.rb[2 * tid] = pf.rb0;
+        L.rb[2 * tid + 1] = pf.rb1;
+        L.ust[tid] = pf.ust;
+        L.nf[tid] = 0;
+        L.rp[tid] = a.rowptr[n];
+        L.rl[tid] = a.rowptr[n + 1] - a.rowptr[n];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            L.xs[d * a.nmax + tid] = a.coords[d * a.N + n];
+            L.racc[d * a.nmax + tid] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kP2PipeMaxPairs; ++q) {
+        const int u = tid + q * kP2Threads;
+        if (u < m.total) L.us[u] = pf.code[q] & 0x7fffffff;
+    }
+    if (tid < m.ne * 25)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) L.lp[4 * tid + b] = (uint16_t)((pf.pos >> (8 * b)) & 0xffu);
+    if (tid < m.ne * 5) {
+        en[2 * tid] = (uint16_t)(pf.enw & 0xffffu);
+        en[2 * tid + 1] = (uint16_t)(pf.enw >> 16);
+    }
+    for (int t = tid; t < 9 * m.total; t += kP2Threads) L.acc[t] = 0.0;
+    __syncthreads();
+    for (int t = tid; t < m.ne * 100; t += kP2Threads) {
+        const int el = t / 100, i = (t - 100 * el) / 10;
+        const int ki = en[el * NPE + i];
+        L.lp[t] = (uint16_t)(L.ust[ki] + popc_below(&L.rb[2 * ki], L.lp[t]));
+    }
+    __syncthreads();
+}
+
+// LDS of the persistent forward beyond the tile kernels' carve-up: the node indices
+size_t p2_pipe_lds_bytes(int nmax, int smax, int T)
+{
+    return p2_lds_bytes(nmax, smax, T, false) + 16 + sizeof(uint16_t) * NPE * T;
+}
+
+template <int MODE, bool F32>
+__global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd_pipe(P2Args a, int64_t nt)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    P2Lds L(smem, a.nmax, a.smax, a.T, false);
+    uint16_t *en = reinterpret_cast<uint16_t *>((reinterpret_cast<uintptr_t>(L.nf + a.nmax) + 15) &
+                                                ~static_cast<uintptr_t>(15));
+    const int tid = threadIdx.x;
+    constexpr int kXcd = 8;
+    const int64_t G = gridDim.x, b = blockIdx.x, x = b % kXcd, j = b / kXcd;
+    const int64_t stride = G / kXcd + (x < G % kXcd ? 1 : 0);
+    const int64_t q = nt / kXcd, r = nt % kXcd;
+    const int64_t first = x * q + (x < r ? x : r), len = q + (x < r ? 1 : 0);
+    const int64_t cnt = len > j ? (len - j + stride - 1) / stride : 0;
+    if (cnt == 0) return;  // the whole workgroup
+    for (int t = tid; t < 14 * 10 * 3; t += kP2Threads) {
+        const int qp = t / 30, i = (t / 3) % 10, mm = t % 3;
+        L.R[t] = sqrt(quad::Tet14::w(qp)) * ref_grad(qp, i, mm);
+    }
+    P2Meta m = p2_meta(a, first + j, true);
+    P2Pre pf;
+    p2_prefetch(a, m, pf);
+    for (int64_t i = 0; i < cnt; ++i) {
+        const int64_t tile = first + j + i * stride;
+        const bool more = i + 1 < cnt;
+        const P2Meta mn = p2_meta(a, tile + stride, more);  // scalar loads, ahead of use
+        __syncthreads();  // the previous tile's global phase has read the LDS lists
+        p2_commit(a, L, en, m, pf);
+        p2_elements<MODE, F32>(a, L, m.e0, m.ne);
+        const P2Meta mc = m;
+        if (more) p2_prefetch(a, mn, pf);  // after the element loop's own global loads
+        m = mn;
+        p2_global<MODE>(a, L, tile, mc.nn, mc.total);
+    }
+}
+
 // A batch of meshes: the work item (mesh << 32) | tile comes from the launch's item list
 // and the mesh's arguments from a device table.
 template <int MODE, bool F32>
@@ -771,6 +927,22 @@ P2Args p2_args(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const
     return a;
 }
 
+// The persistent forward: as many workgroups as stay resident, split evenly over the 8
+// XCDs, each XCD's tiles spread evenly over its workgroups
+template <class K>
+void p2_launch_pipe(K kernel, const fem_pattern *p, P2Args a, size_t lds, hipStream_t s)
+{
+    ensure_lds(kernel, lds);
+    a.tile_list = nullptr;
+    const int64_t nt = p->n_tiles;
+    const int64_t resident = std::max<int64_t>(8, resident_blocks((const void *)kernel, kP2Threads, lds));
+    const int64_t per_xcd = (nt + 7) / 8;
+    int64_t g8 = std::max<int64_t>(1, resident / 8);
+    const int64_t rounds = (per_xcd + g8 - 1) / g8;
+    g8 = std::max<int64_t>(1, (per_xcd + rounds - 1) / rounds);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)(8 * g8)), dim3(kP2Threads), lds, s, a, nt);
+}
+
 template <bool F32>
 void p2_batch_fwd(const BatchFamily &f, const P2Args *t, int mode, size_t lds, hipStream_t s)
 {
@@ -846,7 +1018,17 @@ int p2_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
     const size_t lds = p2_lds_bytes(a.nmax, a.smax, a.T, false);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "P2 tile needs more LDS than a CU has");
     const bool f32 = (flags & FEM_PREC_FP32) != 0;
-    if (mode == kOrdered) {
+    const size_t pl = p2_pipe_lds_bytes(a.nmax, a.smax, a.T);
+    if ((mode == kAtomic || mode == kTwoPass) && a.T <= 8 && a.nmax <= kP2Threads &&
+        a.smax <= kP2PipeMaxPairs * kP2Threads && pl <= 160 * 1024) {
+        if (mode == kAtomic) {
+            if (f32) p2_launch_pipe(k_p2_tile_fwd_pipe<kAtomic, true>, p, a, pl, s);
+            else p2_launch_pipe(k_p2_tile_fwd_pipe<kAtomic, false>, p, a, pl, s);
+        } else {
+            if (f32) p2_launch_pipe(k_p2_tile_fwd_pipe<kTwoPass, true>, p, a, pl, s);
+            else p2_launch_pipe(k_p2_tile_fwd_pipe<kTwoPass, false>, p, a, pl, s);
+        }
+    } else if (mode == kOrdered) {
         if (f32) p2_launch(k_p2_tile_fwd<kOrdered, true>, p, a, mode, lds, s);
         else p2_launch(k_p2_tile_fwd<kOrdered, false>, p, a, mode, lds, s);
     } else if (mode == kColoured) {
