@@ -144,10 +144,11 @@ def _bench_p2(torch, fem, meshgen, dev, steps):
     return out
 
 
-def _bench_batch(torch, fem, meshgen, dev, steps):
-    """512 meshes, n ~ U{6..32}, 6 n^3 tets each, half P1 Helmholtz (kappa, sin load),
-    half P2 elasticity (lambda, mu, body force): one block-diagonal system."""
-    plan = meshgen.batch_plan(512, 6, 32, seed=0)
+def _bench_batch(torch, fem, meshgen, dev, steps, nmin=6, nmax=32):
+    """512 meshes, n ~ U{nmin..nmax}, 6 n^3 tets each, half P1 Helmholtz (kappa, sin load),
+    half P2 elasticity (lambda, mu, body force): one block-diagonal system.  With small
+    meshes (n <= 12) launch overhead dominates the per-mesh loop."""
+    plan = meshgen.batch_plan(512, nmin, nmax, seed=0)
     t0 = time.perf_counter()
     meshes, forms, coefs = [], [], []
     for n, order, kind, seed in plan:
@@ -168,8 +169,8 @@ def _bench_batch(torch, fem, meshgen, dev, steps):
     rhs = torch.empty(b.n_rows, dtype=torch.float64, device=dev)
     vblk = [b.block(values, k) for k in range(len(meshes))]
     rblk = [b.block(rhs, k, rows=True) for k in range(len(meshes))]
-    out = {"workload": "512 meshes, n ~ U{6..32}, 6n^3 tets each, half P1 Helmholtz (sin load), "
-                       "half P2 elasticity (body force); block-diagonal CSR, int64 offsets",
+    out = {"workload": f"512 meshes, n ~ U{{{nmin}..{nmax}}}, 6n^3 tets each, half P1 Helmholtz "
+                       "(sin load), half P2 elasticity (body force); block-diagonal CSR, int64 offsets",
            "n_meshes": len(meshes), "n_elems": E, "n_rows": b.n_rows, "nnz": b.nnz,
            "n_tiles": b.n_tiles, "host_generation_s": gen_s, "batch_build_ms": build_ms}
 
@@ -410,6 +411,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_extra and "batch" in sections and not args.no_batch:
         extra["batch_512"] = _bench_batch(torch, fem, meshgen, dev, args.steps)
+        torch.cuda.empty_cache()
+        extra["batch_512_small"] = _bench_batch(torch, fem, meshgen, dev, args.steps, 6, 12)
         torch.cuda.empty_cache()
     if not args.no_extra:
         out["extra"] = extra

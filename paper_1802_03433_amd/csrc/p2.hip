@@ -200,8 +200,9 @@ struct PairValue {
     int u, ra, cb;
     __device__ PairValue(int t, int total)
     {
-        ra = t / (3 * total);
-        const int rest = t - ra * 3 * total;
+        const int t3 = 3 * total;  // t < 9 total: the row component is 0, 1 or 2
+        ra = (t >= t3 ? 1 : 0) + (t >= 2 * t3 ? 1 : 0);
+        const int rest = t - ra * t3;
         u = rest / 3;
         cb = rest - 3 * u;
     }
@@ -844,6 +845,57 @@ __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd_pipe(P2Args a, int64
 
 // A batch of meshes: the work item (mesh << 32) | tile comes from the launch's item list
 // and the mesh's arguments from a device table.
+
+// The same over a batch's work list (atomic): item w = (member << 32) | tile, the member's
+// arguments from the device table.  The LDS carve-up follows each item's member; the
+// reference gradients and Gram strips sit at its start whatever the member.
+template <bool F32>
+__global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd_pipe_batch(const P2Args *__restrict__ tab,
+                                                                       const int64_t *__restrict__ items,
+                                                                       int64_t n_items)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    constexpr int kXcd = 8;
+    const int64_t G = gridDim.x, b = blockIdx.x, x = b % kXcd, j = b / kXcd;
+    const int64_t stride = G / kXcd + (x < G % kXcd ? 1 : 0);
+    const int64_t q = n_items / kXcd, r = n_items % kXcd;
+    const int64_t first = x * q + (x < r ? x : r), len = q + (x < r ? 1 : 0);
+    const int64_t cnt = len > j ? (len - j + stride - 1) / stride : 0;
+    if (cnt == 0) return;  // the whole workgroup
+    double *R = reinterpret_cast<double *>(smem);
+    for (int t = tid; t < 14 * 10 * 3; t += kP2Threads) {
+        const int qp = t / 30, i = (t / 3) % 10, mm = t % 3;
+        R[t] = sqrt(quad::Tet14::w(qp)) * ref_grad(qp, i, mm);
+    }
+    int64_t w = items[first + j];
+    const P2Args *ap = tab + (w >> 32);
+    int64_t tile = w & 0xffffffffll;
+    P2Meta m = p2_meta(*ap, tile, true);
+    P2Pre pf;
+    p2_prefetch(*ap, m, pf);
+    for (int64_t i = 0; i < cnt; ++i) {
+        const bool more = i + 1 < cnt;
+        const int64_t wn = more ? items[first + j + (i + 1) * stride] : 0;
+        const P2Args *apn = tab + (wn >> 32);
+        const int64_t tilen = wn & 0xffffffffll;
+        const P2Meta mn = p2_meta(*apn, tilen, more);
+        const P2Args &a = *ap;
+        P2Lds L(smem, a.nmax, a.smax, a.T, false);
+        uint16_t *en = reinterpret_cast<uint16_t *>((reinterpret_cast<uintptr_t>(L.nf + a.nmax) + 15) &
+                                                    ~static_cast<uintptr_t>(15));
+        __syncthreads();  // the previous item's global phase has read the LDS lists
+        p2_commit(a, L, en, m, pf);
+        p2_elements<kAtomic, F32>(a, L, m.e0, m.ne);
+        const P2Meta mc = m;
+        if (more) p2_prefetch(*apn, mn, pf);
+        m = mn;
+        p2_global<kAtomic>(a, L, tile, mc.nn, mc.total);
+        ap = apn;
+        tile = tilen;
+    }
+}
+
 template <int MODE, bool F32>
 __global__ __launch_bounds__(kP2Threads) void k_p2_tile_fwd_batch(const P2Args *__restrict__ tab,
                                                                   const int64_t *__restrict__ items,
@@ -946,6 +998,21 @@ void p2_launch_pipe(K kernel, const fem_pattern *p, P2Args a, size_t lds, hipStr
 template <bool F32>
 void p2_batch_fwd(const BatchFamily &f, const P2Args *t, int mode, size_t lds, hipStream_t s)
 {
+    const size_t pl = p2_pipe_lds_bytes(f.nmax, f.smax, f.T);
+    if (mode == kAtomic && f.T <= 8 && f.nmax <= kP2Threads && f.smax <= kP2PipeMaxPairs * kP2Threads &&
+        pl <= 160 * 1024) {
+        auto kernel = k_p2_tile_fwd_pipe_batch<F32>;
+        ensure_lds(kernel, pl);
+        const int64_t n = f.n_items;
+        const int64_t resident = std::max<int64_t>(8, resident_blocks((const void *)kernel, kP2Threads, pl));
+        const int64_t per_xcd = (n + 7) / 8;
+        int64_t g8 = std::max<int64_t>(1, resident / 8);
+        const int64_t rounds = (per_xcd + g8 - 1) / g8;
+        g8 = std::max<int64_t>(1, (per_xcd + rounds - 1) / rounds);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)(8 * g8)), dim3(kP2Threads), pl, s, t,
+                           (const int64_t *)f.items_atomic, n);
+        return;
+    }
     if (mode == kOrdered) launch_batch(k_p2_tile_fwd_batch<kOrdered, F32>, f, t, mode, kP2Threads, lds, s);
     else if (mode == kColoured) launch_batch(k_p2_tile_fwd_batch<kColoured, F32>, f, t, mode, kP2Threads, lds, s);
     else launch_batch(k_p2_tile_fwd_batch<kAtomic, F32>, f, t, mode, kP2Threads, lds, s);
