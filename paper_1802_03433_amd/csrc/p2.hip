@@ -488,6 +488,31 @@ __device__ __forceinline__ void p2_fwd_tile(const P2Args &a, int64_t tile)
 // Entries (r, s) of S_lam = Gb + Gb^T and S_mu = W_mu + W_mu^T for one element, where Gb
 // is the element's block of grad_values and W_mu[(i,a),(j,b)] = Gb[(i,b),(j,a)] +
 // delta_ab sum_c Gb[(i,c),(j,c)] is the adjoint of the mu part of K; zero in the padding.
+// Lane-to-lane move of a double by a DPP control; lanes of rows outside ROWS read 0
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront, returned to every lane, in VALU data-parallel
+// primitives (no LDS crossbar): swaps within quads, half-row and row mirrors give every
+// lane its 16-lane row sum; the row broadcasts of lane 15 into rows 1 and 3 and of lane 31
+// into rows 2 and 3 leave the total in row 3, read from lane 63.
+__device__ __forceinline__ double wave_sum(double x)
+{
+    x += dpp_f64<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
+    x += dpp_f64<0x141, 0xf>(x);  // row_half_mirror
+    x += dpp_f64<0x140, 0xf>(x);  // row_mirror
+    x += dpp_f64<0x142, 0xa>(x);  // row_bcast:15
+    x += dpp_f64<0x143, 0xc>(x);  // row_bcast:31
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 63),
+                            __builtin_amdgcn_readlane(__double2loint(x), 63));
+}
+
 __device__ __forceinline__ void s_entries(const double *acc, const uint16_t *lpe, int r, int c,
                                           double &sl, double &sm)
 {
@@ -600,12 +625,7 @@ __device__ __forceinline__ void p2_bwd_tile(const P2Args &a, int64_t tile)
         }
         // wavefront sums (every lane ends with the totals)
 #pragma unroll
-        for (int v = 0; v < 12; ++v) {
-            double x = red[v];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-            red[v] = x;
-        }
+        for (int v = 0; v < 12; ++v) red[v] = wave_sum(red[v]);
         const double dl = 0.5 * red[0], dm = 0.5 * red[1];
         if (has && lane == 0 && a.gcoef) {
             const int64_t e = a.telem ? a.telem[e0 + el] : e0 + el;
