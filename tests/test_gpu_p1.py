@@ -537,6 +537,40 @@ def test_two_pass_parity_and_reproducibility(name):
     assert all(o == outs[0] for o in outs)
 
 
+def test_two_pass_writes_every_entry():
+    """A non-accumulating two-pass call writes every output entry itself (no zero-fill):
+    the first pass stores the slots and rows held by one tile, the second sums the shared
+    ones and clears the rows of nodes in no element (one isolated node here).  Outputs
+    pre-filled with NaN end up equal to the oracle, forward and adjoint."""
+    m0 = MESHES["tet12"]()
+    coords = np.concatenate([m0.coords, [[2.0], [2.0], [2.0]]], axis=1)
+    m = dataclasses.replace(m0, coords=np.ascontiguousarray(coords))
+    F = fem()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=41)
+    form = F.Form("helmholtz", "sinprod")
+    kap = torch.from_numpy(kappa).cuda()
+    nan = float("nan")
+    v = torch.full((pat.nnz,), nan, dtype=torch.float64, device="cuda")
+    r = torch.full((pat.n_rows,), nan, dtype=torch.float64, device="cuda")
+    F.assemble(pat, d, form, kap, values=v, rhs=r, scatter="two-pass")
+    rp, ci = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
+    assert scaled_close(_np(v), ov, oav, RTOL)[0]
+    assert scaled_close(_np(r), orhs, oar, RTOL)[0]
+    assert _np(r)[-1] == 0.0
+    G, g = meshgen.upstream_grads(pat.nnz, pat.n_rows, seed=41)
+    gk = torch.full_like(kap, nan)
+    gx = torch.full_like(d.coords, nan)
+    F.assemble_backward(pat, d, form, kap, torch.from_numpy(G).cuda(), torch.from_numpy(g).cuda(),
+                        grad_coef=gk, grad_coords=gx, scatter="two-pass")
+    dk, adk, dx, adx = oracle.backward_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci, G, g)
+    assert scaled_close(_np(gk)[0], dk, adk, RTOL)[0]
+    assert scaled_close(_np(gx), dx, adx, RTOL)[0]
+    assert np.all(_np(gx)[:, -1] == 0.0)
+
+
 def test_two_pass_full_size():
     m, kappa, rp, ci, (ov, orhs, oav, oar) = c1()
     F = fem()
