@@ -65,8 +65,13 @@ extern "C" {
 
 /* ---- flags ---- */
 #define FEM_SCATTER_ATOMIC 0x0u   /* scatter with device-scope FP64 atomic adds */
-#define FEM_SCATTER_COLOURED 0x1u /* colour by colour, plain read-modify-write:
-                                     bitwise reproducible run to run */
+#define FEM_SCATTER_COLOURED 0x1u /* colour by colour (tiles of one colour share no
+                                     node), each tile's sums applied with plain
+                                     read-modify-writes: bitwise reproducible run to run.
+                                     Inside a P1 tile the contributions add exactly as
+                                     int64 fixed point with a scale per slot (each term
+                                     rounded below 2^-51 of the slot's largest term in
+                                     the tile); P2 tiles add their elements in order */
 #define FEM_ACCUMULATE 0x2u       /* add into the outputs instead of overwriting them */
 #define FEM_VALIDATE 0x4u         /* device-side input checks (synchronises) */
 #define FEM_PREC_FP32 0x8u        /* elasticity: element-matrix contraction on FP32 matrix
@@ -82,8 +87,9 @@ extern "C" {
                                      lower-colour neighbours -- same sums, same bits */
 #define FEM_SCATTER_TWO_PASS 0x80u /* deterministic scatter in two passes, without colour
                                       order: each tile stores its per-slot partial sums
-                                      (elements added in a fixed order), then every slot
-                                      and row sums its partials in ascending tile order.
+                                      (formed as for FEM_SCATTER_COLOURED), then every
+                                      slot and row sums its partials in ascending tile
+                                      order.
                                       Bitwise reproducible run to run.  The first call
                                       allocates the pattern's partial-sum buffers (not
                                       under stream capture).  Not combined with
@@ -170,8 +176,9 @@ void fem_pattern_destroy(fem_pattern *pattern);
  * then the scatter-add of the element matrix and vector into values and rhs.
  *   values: double [nnz] in the order of fem_pattern_export's colind.
  *   rhs:    double [n_rows], may be NULL when form->load == FEM_LOAD_NONE.
- * flags: FEM_SCATTER_ATOMIC or FEM_SCATTER_COLOURED, optionally FEM_ACCUMULATE
- * (otherwise values and rhs are zero-filled first, on the stream) and FEM_VALIDATE.
+ * flags: FEM_SCATTER_ATOMIC, FEM_SCATTER_COLOURED (optionally FEM_COLOUR_LAUNCHES) or
+ * FEM_SCATTER_TWO_PASS; optionally FEM_ACCUMULATE (otherwise values and rhs are
+ * overwritten), FEM_VALIDATE, FEM_PREC_FP32 (elasticity), FEM_ELEMENT_SCATTER.
  * The mesh must have the connectivity the pattern was built from (same pointer
  * contents and sizes); coordinates and coefficients may change between calls.
  * Errors: INVALID_ARG, UNSUPPORTED (form/element combination), DEGENERATE
@@ -190,7 +197,7 @@ int fem_assemble(const fem_pattern *pattern, const fem_mesh *mesh, const fem_for
  *   grad_coords [dim][n_nodes]: dL/dcoords, overwritten (or added to); NULL = not
  *     requested.  For P2 only vertex nodes receive gradient (edge-node coordinates are
  *     not read by the forward pass).
- * The scatter of grad_coords follows FEM_SCATTER_ATOMIC / FEM_SCATTER_COLOURED.
+ * The scatter of grad_coords follows the scatter flags as in fem_assemble.
  */
 int fem_assemble_backward(const fem_pattern *pattern, const fem_mesh *mesh,
                           const fem_form *form, const double *coef,
