@@ -200,6 +200,15 @@ def test_batch_rejects_mixed_loads_in_a_family():
     assert ei.value.code == -2
 
 
+def test_batch_rejects_two_pass():
+    """The batched entry points take the atomic and coloured scatters only."""
+    F, hm, dm, forms, coefs = _small_batch(3)
+    b = F.Batch(dm)
+    with pytest.raises(F.FemError) as ei:
+        F.assemble_batch(b, dm, forms, coefs, scatter="two-pass")
+    assert ei.value.code == -1
+
+
 def _c4_plan():
     return meshgen.batch_plan(512, 6, 32, seed=0)
 
