@@ -234,7 +234,7 @@ int scan_counts_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s)
     hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n, sums,
                        out);
     hipError_t e = hipGetLastError();
-    hipFreeAsync(sums, s);
+    (void)hipFreeAsync(sums, s);
     if (e != hipSuccess) return fail(FEM_ERR_HIP, std::string("scan: ") + hipGetErrorString(e));
     return FEM_OK;
 }

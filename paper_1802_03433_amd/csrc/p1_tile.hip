@@ -304,7 +304,6 @@ template <int D, int LOAD, int MODE>
 __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
 {
     constexpr int NP = D + 1;
-    using R = quad::P1Rule<D>;
     extern __shared__ __align__(16) unsigned char smem[];
     Lds<D> L(smem, a.nmax, a.smax);
     const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];

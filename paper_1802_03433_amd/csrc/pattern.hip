@@ -305,7 +305,7 @@ struct Tmp {
     }
     ~Tmp()
     {
-        for (void *q : ptrs) hipFreeAsync(q, s);
+        for (void *q : ptrs) (void)hipFreeAsync(q, s);
     }
 };
 

@@ -494,7 +494,7 @@ struct TmpT {
     }
     ~TmpT()
     {
-        for (void *q : ptrs) hipFreeAsync(q, s);
+        for (void *q : ptrs) (void)hipFreeAsync(q, s);
     }
 };
 
@@ -703,7 +703,6 @@ int build_tile_plan(fem_pattern *p, const int32_t *conn, const int32_t *slot, co
     // distinct-slot lists (after the first-writer masks)
     {
         int32_t *scnt = nullptr;
-        int64_t *sptr64 = nullptr;
         FEM_TRY(tmp.get(&scnt, nt));
         FEM_TRY(pattern_alloc(p, (void **)&p->tslot_ptr, sizeof(int64_t) * (nt + 1)));
         FEM_TRY(pattern_alloc(p, (void **)&p->tust, sizeof(int32_t) * n_tn));
