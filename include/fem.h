@@ -38,6 +38,7 @@
 #ifndef FEM_H
 #define FEM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -282,6 +283,29 @@ int fem_assemble_backward_batch(fem_batch *batch, const fem_mesh *meshes, const 
 
 /* Releases a batch and its patterns (NULL is ignored).  Synchronises the device first. */
 void fem_batch_destroy(fem_batch *batch);
+
+/* Registers the allocator for the library's own device memory: the arrays a pattern or
+ * batch handle holds (rowptr, colind, element-to-slot map, tile plan, colour lists, and
+ * the partial sums of FEM_SCATTER_TWO_PASS, drawn at a pattern's first such call).  Not
+ * an operation of the paper; it is for callers whose framework manages device memory
+ * itself (a caching allocator), so that a handle's memory shows in that framework's
+ * accounting and is reused by it.
+ *   alloc(bytes, ctx): returns device memory of at least `bytes` bytes on the current
+ *     HIP device, 256-byte aligned, or NULL: the calling function then fails with
+ *     FEM_ERR_OOM (a failed build releases what it had drawn).
+ *   release(ptr, ctx): returns one pointer that alloc gave.  It is called from
+ *     fem_pattern_destroy / fem_batch_destroy after they synchronise the device, with
+ *     the handle's device current.
+ *   ctx: passed through unchanged; owned by the caller, who keeps it alive while any
+ *     handle built under it exists.
+ * Both functions NULL restores the default (hipMalloc / hipFree).  Exactly one NULL is
+ * FEM_ERR_INVALID_ARG and changes nothing.  The setting is process-wide and applies to
+ * allocations made afterwards; each buffer is released through the allocator it was
+ * drawn from.  Scratch memory that lives within one call stays on hipMallocAsync of the
+ * call's stream.  Safe to call from any thread; not during a build on another thread if
+ * that build must see one particular setting. */
+int fem_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                      void (*release)(void *ptr, void *ctx), void *ctx);
 
 /* Static description of a return code. */
 const char *fem_error_string(int code);

@@ -1,7 +1,7 @@
 """MI355X (gfx950) finite element assembly: HIP kernels behind a C ABI (include/fem.h).
 
 Importing the package loads libfemhip.so; it raises ImportError when the library has
-not been built (python -m paper_1802_03433_amd.build).  There is no CPU fallback.
+not been built (python paper_1802_03433_amd/build.py).  There is no CPU fallback.
 """
 
 from .api import (  # noqa: F401
@@ -15,5 +15,7 @@ from .api import (  # noqa: F401
     assemble_backward_batch,
     assemble_batch,
     fem_assemble,
+    set_allocator,
+    use_torch_allocator,
 )
 from ._lib import FemError  # noqa: F401

@@ -70,6 +70,7 @@ EXPORTS = (
     "fem_assemble_batch",
     "fem_assemble_backward_batch",
     "fem_batch_destroy",
+    "fem_set_allocator",
     "fem_error_string",
     "fem_last_error_message",
 )
@@ -126,11 +127,17 @@ class fem_batch_info(ctypes.Structure):
     ]
 
 
+# fem_set_allocator's callbacks: alloc(bytes, ctx) -> device pointer or NULL,
+# release(ptr, ctx).
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(
             f"libfemhip.so not found at {path}; build it with "
-            "`python -m paper_1802_03433_amd.build` (hipcc, gfx950)"
+            "`python paper_1802_03433_amd/build.py` (hipcc, gfx950)"
         )
     L = ctypes.CDLL(path)
     P = ctypes.c_void_p
@@ -152,6 +159,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fem_assemble_backward_batch.argtypes = [P, pm, pf, P, P, P, P, P, ctypes.c_uint, P]
     L.fem_batch_destroy.argtypes = [P]
     L.fem_batch_destroy.restype = None
+    L.fem_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, P]
     L.fem_error_string.argtypes = [ctypes.c_int]
     L.fem_error_string.restype = ctypes.c_char_p
     L.fem_last_error_message.argtypes = []
@@ -159,7 +167,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for n in ("fem_build_pattern", "fem_pattern_query", "fem_pattern_export",
               "fem_pattern_colours", "fem_assemble", "fem_assemble_backward",
               "fem_build_batch", "fem_batch_query", "fem_batch_offsets", "fem_batch_export",
-              "fem_assemble_batch", "fem_assemble_backward_batch"):
+              "fem_assemble_batch", "fem_assemble_backward_batch", "fem_set_allocator"):
         getattr(L, n).restype = ctypes.c_int
     return L
 

@@ -22,6 +22,49 @@ _SCATTER = {"atomic": L.SCATTER_ATOMIC, "coloured": L.SCATTER_COLOURED,
             "two-pass": L.SCATTER_TWO_PASS}
 
 
+# Every callback pair ever registered with fem_set_allocator stays referenced for the
+# life of the process: a handle releases its memory through the pair it drew it from,
+# possibly long after another pair (or the default) was registered.
+_registered = []
+
+
+def set_allocator(alloc=None, release=None):
+    """Registers Python callables for the device memory of pattern and batch handles
+    built from now on: alloc(nbytes) -> int device address (0 or an exception: the
+    build fails with FemError FEM_ERR_OOM), release(address).  Both None restores
+    hipMalloc / hipFree."""
+    if (alloc is None) != (release is None):
+        raise ValueError("give both alloc and release, or neither")
+    if alloc is None:
+        L.check(L.lib.fem_set_allocator(L.ALLOC_FN(), L.RELEASE_FN(), None), "fem_set_allocator")
+        return
+
+    def c_alloc(nbytes, _ctx):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception:
+            return None
+
+    def c_release(ptr, _ctx):
+        try:
+            release(int(ptr))
+        except Exception:
+            pass
+
+    pair = (L.ALLOC_FN(c_alloc), L.RELEASE_FN(c_release))
+    _registered.append(pair)
+    L.check(L.lib.fem_set_allocator(pair[0], pair[1], None), "fem_set_allocator")
+
+
+def use_torch_allocator():
+    """Handle memory from torch's caching allocator on the current device and stream, so
+    that it counts in torch.cuda.memory_allocated() and returns to torch's pool when the
+    handle is closed."""
+    set_allocator(
+        lambda n: torch.cuda.caching_allocator_alloc(n, torch.cuda.current_device()),
+        torch.cuda.caching_allocator_delete)
+
+
 def _stream_ptr(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 

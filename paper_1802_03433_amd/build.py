@@ -1,6 +1,7 @@
 """Builds libfemhip.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1802_03433_amd.build   (or call build()).
+Usage: python paper_1802_03433_amd/build.py   (or call build()).  Run as a file, not with
+-m: importing the package loads the library this script builds.
 Objects go to <repo>/_build/, the shared library next to this file.
 """
 

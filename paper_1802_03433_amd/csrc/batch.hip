@@ -18,17 +18,7 @@ namespace {
 
 int batch_alloc(fem_batch *b, void **ptr, size_t bytes)
 {
-    *ptr = nullptr;
-    if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(ptr, bytes);
-    if (e != hipSuccess) {
-        *ptr = nullptr;
-        return fail(e == hipErrorOutOfMemory ? FEM_ERR_OOM : FEM_ERR_HIP,
-                    std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
-    }
-    b->owned.push_back(DevBuf{*ptr, bytes});
-    b->device_bytes += (int64_t)bytes;
-    return FEM_OK;
+    return device_alloc(b->owned, b->device_bytes, ptr, bytes);
 }
 
 int family_of(const fem_pattern *p)
@@ -403,7 +393,7 @@ void fem_batch_destroy(fem_batch *b)
     (void)hipSetDevice(b->device);
     (void)hipDeviceSynchronize();
     for (fem_pattern *p : b->pats) fem_pattern_destroy(p);
-    for (auto &d : b->owned) (void)hipFree(d.ptr);
+    for (auto &d : b->owned) device_free(d);
     if (b->staging) (void)hipHostFree(b->staging);
     (void)hipSetDevice(cur);
     delete b;

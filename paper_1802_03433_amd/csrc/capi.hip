@@ -225,6 +225,16 @@ int fem_pattern_colours(const fem_pattern *p, int32_t *colour, void *stream)
     return FEM_OK;
 }
 
+int fem_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*release)(void *ptr, void *ctx),
+                      void *ctx)
+{
+    clear_error();
+    if ((alloc == nullptr) != (release == nullptr))
+        return fail(FEM_ERR_INVALID_ARG, "fem_set_allocator: give both functions or neither");
+    set_allocator(alloc, release, ctx);
+    return FEM_OK;
+}
+
 void fem_pattern_destroy(fem_pattern *p)
 {
     if (!p) return;
@@ -232,7 +242,7 @@ void fem_pattern_destroy(fem_pattern *p)
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
-    for (auto &b : p->owned) (void)hipFree(b.ptr);
+    for (auto &b : p->owned) device_free(b);
     (void)hipSetDevice(cur);
     delete p;
 }

@@ -46,20 +46,60 @@ int64_t resident_blocks(const void *kernel, int threads, size_t lds)
     return n;
 }
 
-int pattern_alloc(fem_pattern *p, void **ptr, size_t bytes)
+namespace {
+struct Allocator {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*release)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+}  // namespace
+
+void set_allocator(void *(*alloc)(size_t, void *), void (*release)(void *, void *), void *ctx)
+{
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    g_alloc = Allocator{alloc, release, ctx};
+}
+
+int device_alloc(std::vector<DevBuf> &owned, int64_t &device_bytes, void **ptr, size_t bytes)
 {
     *ptr = nullptr;
     if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(ptr, bytes);
-    if (e != hipSuccess) {
-        *ptr = nullptr;
-        return fail(e == hipErrorOutOfMemory ? FEM_ERR_OOM : FEM_ERR_HIP,
-                    std::string("hipMalloc(") + std::to_string(bytes) +
-                        "): " + hipGetErrorString(e));
+    Allocator a;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        a = g_alloc;
     }
-    p->owned.push_back(DevBuf{*ptr, bytes});
-    p->device_bytes += (int64_t)bytes;
+    if (a.alloc) {
+        *ptr = a.alloc(bytes, a.ctx);
+        if (!*ptr)
+            return fail(FEM_ERR_OOM, std::string("registered allocator returned NULL for ") +
+                                         std::to_string(bytes) + " bytes");
+    } else {
+        hipError_t e = hipMalloc(ptr, bytes);
+        if (e != hipSuccess) {
+            *ptr = nullptr;
+            return fail(e == hipErrorOutOfMemory ? FEM_ERR_OOM : FEM_ERR_HIP,
+                        std::string("hipMalloc(") + std::to_string(bytes) +
+                            "): " + hipGetErrorString(e));
+        }
+    }
+    owned.push_back(DevBuf{*ptr, bytes, a.alloc ? a.release : nullptr, a.ctx});
+    device_bytes += (int64_t)bytes;
     return FEM_OK;
+}
+
+void device_free(const DevBuf &b)
+{
+    if (!b.ptr) return;
+    if (b.release) b.release(b.ptr, b.ctx);
+    else (void)hipFree(b.ptr);
+}
+
+int pattern_alloc(fem_pattern *p, void **ptr, size_t bytes)
+{
+    return device_alloc(p->owned, p->device_bytes, ptr, bytes);
 }
 
 // ---------------------------------------------------------------------------------------

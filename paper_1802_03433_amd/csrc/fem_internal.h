@@ -63,6 +63,8 @@ inline int scatter_mode(unsigned flags)
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    void (*release)(void *, void *) = nullptr;  // the caller allocator's free, or NULL: hipFree
+    void *ctx = nullptr;
 };
 
 // Colour limit of the first-fit colouring (two 64-bit masks per element).
@@ -220,6 +222,11 @@ int p2_tile_batch(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fe
 
 // allocation owned by a pattern
 int pattern_alloc(fem_pattern *p, void **ptr, size_t bytes);
+// Device memory of pattern and batch handles: from the allocator registered with
+// fem_set_allocator, else hipMalloc; recorded in `owned` with the way to release it.
+int device_alloc(std::vector<DevBuf> &owned, int64_t &device_bytes, void **ptr, size_t bytes);
+void device_free(const DevBuf &b);
+void set_allocator(void *(*alloc)(size_t, void *), void (*release)(void *, void *), void *ctx);
 
 // exclusive scan of n int32 counts into out[0..n] (out[n] = total), int64 accumulation
 int scan_counts_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);

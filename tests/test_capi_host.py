@@ -69,3 +69,27 @@ def test_null_arguments_rejected_before_device_work(L):
     assert L.lib.fem_assemble(None, ctypes.byref(m), ctypes.byref(f), None, None, None, 0, None) == -1
     assert L.lib.fem_pattern_query(None, None) == -1
     L.lib.fem_pattern_destroy(None)  # no-op
+
+
+def test_set_allocator_arguments(L):
+    calls = []
+    alloc = L.ALLOC_FN(lambda n, ctx: calls.append(n) or None)
+    release = L.RELEASE_FN(lambda p, ctx: calls.append(p))
+    # exactly one function is an argument error and leaves the setting alone
+    assert L.lib.fem_set_allocator(alloc, L.RELEASE_FN(), None) == -1
+    assert b"both" in L.lib.fem_last_error_message()
+    assert L.lib.fem_set_allocator(L.ALLOC_FN(), release, None) == -1
+    assert L.lib.fem_set_allocator(alloc, release, None) == 0
+    assert L.lib.fem_last_error_message() == b""
+    assert L.lib.fem_set_allocator(L.ALLOC_FN(), L.RELEASE_FN(), None) == 0
+    assert calls == []  # registering calls neither function
+
+
+def test_set_allocator_python_arguments():
+    import paper_1802_03433_amd as fem
+
+    with pytest.raises(ValueError):
+        fem.set_allocator(alloc=lambda n: 0)
+    with pytest.raises(ValueError):
+        fem.set_allocator(release=lambda p: None)
+    fem.set_allocator()  # back to the default
