@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "fem_oracle.c")
 LIB = os.path.join(_HERE, "libfem_oracle.so")
 
-LOAD = {"none": 0, "const": 1, "sinprod": 2}
+LOAD = {"none": 0, "const": 1, "sinprod": 2, "poly2": 3}
 
 _lib = None
 
@@ -53,6 +53,11 @@ def lib() -> ctypes.CDLL:
         L.fo_element_p1.argtypes = [i32, P, dbl, dbl, P]
         L.fo_assemble_p1.argtypes = [i32, i64, i64, P, P, P, dbl, i32, P, P, P, P, P, P, P]
         L.fo_backward_p1.argtypes = [i32, i64, i64, P, P, P, dbl, i32, P, P, P, P, P, P, P, P, P]
+        L.fo_element_p1_sigma.argtypes = [i32, P, dbl, dbl, P, P]
+        L.fo_assemble_p1_general.argtypes = [i32, i64, i64, P, P, P, dbl, P, i32, P, P, P, P,
+                                             P, P, P, P]
+        L.fo_backward_p1_general.argtypes = [i32, i64, i64, P, P, P, dbl, P, i32, P, P, P, P,
+                                             P, P, P, P, P, P]
         L.fo_element_p2_elasticity.argtypes = [P, dbl, dbl, P]
         L.fo_p2_phi_mean.argtypes = [P]
         L.fo_assemble_p2_elasticity.argtypes = [i64, i64, P, P, P, P, i32, P, P, P, P, P, P, P]
@@ -60,7 +65,8 @@ def lib() -> ctypes.CDLL:
             i64, i64, P, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, P
         ]
         for name in ("fo_signed_volumes", "fo_element_p1", "fo_p2_phi_mean",
-                     "fo_assemble_p1", "fo_backward_p1", "fo_element_p2_elasticity",
+                     "fo_assemble_p1", "fo_backward_p1", "fo_element_p1_sigma",
+                     "fo_assemble_p1_general", "fo_backward_p1_general", "fo_element_p2_elasticity",
                      "fo_assemble_p2_elasticity", "fo_backward_p2_elasticity"):
             getattr(L, name).restype = i32
         _lib = L
@@ -131,6 +137,36 @@ def element_p1(xv, kappa=1.0, c=0.0):
     return A.reshape(d + 1, d + 1)
 
 
+def _sigma(sigma):
+    """sigma: None, or [4][3][3] (S0, S_x, S_y, S_z; 2D reads the leading 2x2 blocks)."""
+    if sigma is None:
+        return None
+    s = np.zeros((4, 3, 3))
+    a = np.asarray(sigma, dtype=np.float64)
+    s[: a.shape[0], : a.shape[1], : a.shape[2]] = a
+    return s.ravel()
+
+
+def _poly(poly):
+    """poly: coefficients of 1, x, y, z, x^2, xy, xz, y^2, yz, z^2."""
+    if poly is None:
+        return None
+    p = np.zeros(10)
+    a = np.asarray(poly, dtype=np.float64).ravel()
+    p[: a.size] = a
+    return p
+
+
+def element_p1_sigma(xv, sigma, kappa=1.0, c=0.0):
+    """One element of the matrix-coefficient form (no load)."""
+    xv = _f64(xv)
+    d = xv.shape[1]
+    A = np.zeros((d + 1) * (d + 1))
+    _check(lib().fo_element_p1_sigma(d, _p(xv), kappa, c, _p(_sigma(sigma)), _p(A)),
+           "element_p1_sigma")
+    return A.reshape(d + 1, d + 1)
+
+
 def element_p2_elasticity(xv, lam, mu):
     xv = _f64(xv)
     K = np.zeros(900)
@@ -144,8 +180,9 @@ def p2_phi_mean():
     return out
 
 
-def assemble_p1(mesh, kappa, c, load, load_const, rowptr, colind):
-    """Returns (values, rhs, abs_values, abs_rhs)."""
+def assemble_p1(mesh, kappa, c, load, load_const, rowptr, colind, sigma=None, poly=None):
+    """Returns (values, rhs, abs_values, abs_rhs).  sigma: None (kappa I) or the affine
+    matrix field [4][3][3]; poly: the quadratic load's coefficients (load "poly2")."""
     coords = _f64(mesh.coords)
     conn = _i32(mesh.conn)
     kappa = _f64(kappa).ravel()
@@ -154,13 +191,16 @@ def assemble_p1(mesh, kappa, c, load, load_const, rowptr, colind):
     vals, avals = np.zeros(nnz), np.zeros(nnz)
     rhs, arhs = np.zeros(N), np.zeros(N)
     lc = _f64(np.atleast_1d(load_const if load_const is not None else [0.0]))
-    _check(lib().fo_assemble_p1(mesh.dim, N, E, _p(coords), _p(conn), _p(kappa), float(c),
-                                LOAD[load], _p(lc), _p(rowptr), _p(colind), _p(vals), _p(rhs),
-                                _p(avals), _p(arhs)), "assemble_p1")
+    sg, pl = _sigma(sigma), _poly(poly)
+    _check(lib().fo_assemble_p1_general(mesh.dim, N, E, _p(coords), _p(conn), _p(kappa),
+                                        float(c), _p(sg), LOAD[load], _p(lc), _p(pl),
+                                        _p(rowptr), _p(colind), _p(vals), _p(rhs), _p(avals),
+                                        _p(arhs)), "assemble_p1")
     return vals, rhs, avals, arhs
 
 
-def backward_p1(mesh, kappa, c, load, load_const, rowptr, colind, Gbar, gbar, want_coords=True):
+def backward_p1(mesh, kappa, c, load, load_const, rowptr, colind, Gbar, gbar, want_coords=True,
+                sigma=None, poly=None):
     """Returns (dkappa, abs_dkappa, dcoords [d][N], abs_dcoords [d][N])."""
     coords = _f64(mesh.coords)
     conn = _i32(mesh.conn)
@@ -172,9 +212,11 @@ def backward_p1(mesh, kappa, c, load, load_const, rowptr, colind, Gbar, gbar, wa
     lc = _f64(np.atleast_1d(load_const if load_const is not None else [0.0]))
     Gbar = None if Gbar is None else _f64(Gbar)
     gbar = None if gbar is None else _f64(gbar)
-    _check(lib().fo_backward_p1(d, N, E, _p(coords), _p(conn), _p(kappa), float(c), LOAD[load],
-                                _p(lc), _p(rowptr), _p(colind), _p(Gbar), _p(gbar), _p(dk),
-                                _p(adk), _p(dx), _p(adx)), "backward_p1")
+    sg, pl = _sigma(sigma), _poly(poly)
+    _check(lib().fo_backward_p1_general(d, N, E, _p(coords), _p(conn), _p(kappa), float(c),
+                                        _p(sg), LOAD[load], _p(lc), _p(pl), _p(rowptr),
+                                        _p(colind), _p(Gbar), _p(gbar), _p(dk), _p(adk), _p(dx),
+                                        _p(adx)), "backward_p1")
     return dk, adk, dx, adx
 
 

@@ -16,6 +16,12 @@
  *   - Sec. 5 (sparse variant): the stored matrix keeps, per row, exactly the columns
  *     of the nodes that share an element with the row's node (the paper's
  *     gNbrNodeLen / gNbrNodeIdx arrays); here those lists are stored as CSR.
+ *   - Sec. 4.2's worked example keeps the matrix coefficient: sigma(x) is a (not
+ *     necessarily symmetric) 2x2 matrix field, affine in x there, with a quadratic right
+ *     hand side.  The oracle takes sigma(x) = S0 + sum_a x_a S_a (one 3x3 matrix per
+ *     term; 2D uses the leading 2x2 blocks), scaled per element by kappa, and a load f
+ *     that is any quadratic polynomial in x.  Row i of A is the test function l_i and
+ *     column j the trial function l_j:  A_ij = int kappa grad l_i . sigma grad l_j + ...
  *   - Sec. 7 names higher-order approximations as the next step: isotropic linear
  *     elasticity with Lagrange P2 tetrahedra, the same assembly structure with 3
  *     interleaved components per node (dof = 3*node + component).
@@ -33,7 +39,9 @@
  * Conventions shared with the mesh generator (input format, not method):
  *   coords SoA [dim][n_nodes]; conn SoA [npe][n_elems]; P2 local order: vertices
  *   0..3, then edge nodes of edges (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).
- *   load kinds: 0 = none, 1 = constant (per component), 2 = prod_a sin(pi x_a).
+ *   load kinds: 0 = none, 1 = constant (per component), 2 = prod_a sin(pi x_a),
+ *   3 = quadratic polynomial with coefficients of 1, x, y, z, x^2, xy, xz, y^2, yz, z^2.
+ *   sigma: 4 row-major 3x3 matrices S0, S_x, S_y, S_z (NULL: the identity).
  */
 #include <complex.h>
 #include <math.h>
@@ -50,6 +58,7 @@
 #define LOAD_NONE 0
 #define LOAD_CONST 1
 #define LOAD_SINPROD 2
+#define LOAD_POLY2 3
 
 typedef double complex cplx;
 
@@ -459,22 +468,141 @@ static cplx f_sinprod_c(int d, const cplx *xq)
     return f;
 }
 
-static void p1_element_real(int d, const double x[4][3], double kappa, double c, int load,
-                            double fconst, const rule_t *rule, double A[16], double bvec[4],
-                            double *vol_out)
+/* (1/|T|) int_T x_a = sum_k x_k[a] (1/|T|) int_T l_k  (the monomial formula) */
+static void mean_coords_real(int d, const double x[4][3], double m[3])
+{
+    for (int a = 0; a < 3; ++a) m[a] = 0.0;
+    for (int k = 0; k <= d; ++k) {
+        int alpha[4] = {0, 0, 0, 0};
+        alpha[k] = 1;
+        double lk = fo_simplex_monomial(d, alpha);
+        for (int a = 0; a < d; ++a) m[a] += x[k][a] * lk;
+    }
+}
+
+static void mean_coords_cplx(int d, cplx x[4][3], cplx m[3])
+{
+    for (int a = 0; a < 3; ++a) m[a] = 0.0;
+    for (int k = 0; k <= d; ++k) {
+        int alpha[4] = {0, 0, 0, 0};
+        alpha[k] = 1;
+        double lk = fo_simplex_monomial(d, alpha);
+        for (int a = 0; a < d; ++a) m[a] += x[k][a] * lk;
+    }
+}
+
+/* S = (1/|T|) int_T sigma(x) = S0 + sum_a S_a (1/|T|) int_T x_a  (sigma is affine in x) */
+static void sigma_mean_real(int d, const double x[4][3], const double *sig, double S[3][3])
+{
+    double m[3];
+    mean_coords_real(d, x, m);
+    for (int r = 0; r < d; ++r)
+        for (int q = 0; q < d; ++q) {
+            double v = sig[r * 3 + q];
+            for (int a = 0; a < d; ++a) v += sig[(1 + a) * 9 + r * 3 + q] * m[a];
+            S[r][q] = v;
+        }
+}
+
+static void sigma_mean_cplx(int d, cplx x[4][3], const double *sig, cplx S[3][3])
+{
+    cplx m[3];
+    mean_coords_cplx(d, x, m);
+    for (int r = 0; r < d; ++r)
+        for (int q = 0; q < d; ++q) {
+            cplx v = sig[r * 3 + q];
+            for (int a = 0; a < d; ++a) v += sig[(1 + a) * 9 + r * 3 + q] * m[a];
+            S[r][q] = v;
+        }
+}
+
+/* index of the coefficient of x_a x_b (a <= b) in the quadratic load */
+static int poly2_index(int a, int b)
+{
+    static const int Q[3][3] = {{4, 5, 6}, {5, 7, 8}, {6, 8, 9}};
+    return Q[a][b];
+}
+
+/* (1/|T|) int_T f l_i for the quadratic load f, exactly: with x_a = sum_k l_k x_k[a],
+ * every term is a barycentric monomial of degree <= 3 (the monomial formula) */
+static double poly2_load_real(int d, const double x[4][3], const double *p, int i)
+{
+    int np = d + 1;
+    int al[4] = {0, 0, 0, 0};
+    al[i] = 1;
+    double t = p[0] * fo_simplex_monomial(d, al);
+    for (int a = 0; a < d; ++a)
+        for (int k = 0; k < np; ++k) {
+            int b2[4] = {0, 0, 0, 0};
+            b2[i] += 1;
+            b2[k] += 1;
+            t += p[1 + a] * x[k][a] * fo_simplex_monomial(d, b2);
+        }
+    for (int a = 0; a < d; ++a)
+        for (int b = a; b < d; ++b)
+            for (int k = 0; k < np; ++k)
+                for (int l = 0; l < np; ++l) {
+                    int b3[4] = {0, 0, 0, 0};
+                    b3[i] += 1;
+                    b3[k] += 1;
+                    b3[l] += 1;
+                    t += p[poly2_index(a, b)] * x[k][a] * x[l][b] * fo_simplex_monomial(d, b3);
+                }
+    return t;
+}
+
+static cplx poly2_load_cplx(int d, cplx x[4][3], const double *p, int i)
+{
+    int np = d + 1;
+    int al[4] = {0, 0, 0, 0};
+    al[i] = 1;
+    cplx t = p[0] * fo_simplex_monomial(d, al);
+    for (int a = 0; a < d; ++a)
+        for (int k = 0; k < np; ++k) {
+            int b2[4] = {0, 0, 0, 0};
+            b2[i] += 1;
+            b2[k] += 1;
+            t += p[1 + a] * x[k][a] * fo_simplex_monomial(d, b2);
+        }
+    for (int a = 0; a < d; ++a)
+        for (int b = a; b < d; ++b)
+            for (int k = 0; k < np; ++k)
+                for (int l = 0; l < np; ++l) {
+                    int b3[4] = {0, 0, 0, 0};
+                    b3[i] += 1;
+                    b3[k] += 1;
+                    b3[l] += 1;
+                    t += p[poly2_index(a, b)] * x[k][a] * x[l][b] * fo_simplex_monomial(d, b3);
+                }
+    return t;
+}
+
+/* sigma == NULL: the identity (kappa I); poly: the LOAD_POLY2 coefficients */
+static void p1_element_real(int d, const double x[4][3], double kappa, double c,
+                            const double *sig, int load, double fconst, const double *poly,
+                            const rule_t *rule, double A[16], double bvec[4], double *vol_out)
 {
     double B[4][3];
     double det = geom_real(d, x, B);
     double vol = fabs(det) / factorial(d);
     int np = d + 1;
+    double S[3][3];
+    if (sig) sigma_mean_real(d, x, sig, S);
     for (int i = 0; i < np; ++i)
         for (int j = 0; j < np; ++j) {
             double g = 0.0;
-            for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
+            if (sig) {
+                for (int a = 0; a < d; ++a)
+                    for (int b = 0; b < d; ++b) g += B[i][a] * S[a][b] * B[j][b];
+            } else {
+                for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
+            }
             A[i * np + j] = kappa * vol * g + c * vol * mass_p1_ref(d, i, j);
         }
     for (int i = 0; i < np; ++i) bvec[i] = 0.0;
-    if (load == LOAD_CONST) {
+    if (load == LOAD_POLY2) {
+        for (int i = 0; i < np; ++i) bvec[i] = vol * poly2_load_real(d, x, poly, i);
+    } else if (load == LOAD_CONST) {
         for (int i = 0; i < np; ++i) bvec[i] = fconst * vol / (double)(d + 1);
     } else if (load == LOAD_SINPROD) {
         for (int q = 0; q < rule->n; ++q) {
@@ -502,16 +630,32 @@ int fo_element_p1(int d, const double *xv, double kappa, double c, double *A)
     for (int k = 0; k <= d; ++k)
         for (int a = 0; a < d; ++a) x[k][a] = xv[k * d + a];
     double b[4];
-    p1_element_real(d, x, kappa, c, LOAD_NONE, 0.0, NULL, A, b, NULL);
+    p1_element_real(d, x, kappa, c, NULL, LOAD_NONE, 0.0, NULL, NULL, A, b, NULL);
     return FO_OK;
 }
 
-int fo_assemble_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords,
-                   const int32_t *conn, const double *kappa, double c, int load,
-                   const double *load_const, const int64_t *rowptr, const int32_t *colind,
-                   double *values, double *rhs, double *abs_values, double *abs_rhs)
+/* One element of the sigma form (sigma: 36 doubles as above), no load. */
+int fo_element_p1_sigma(int d, const double *xv, double kappa, double c, const double *sigma,
+                        double *A)
+{
+    if ((d != 2 && d != 3) || !sigma) return FO_ERR_ARG;
+    double x[4][3] = {{0}};
+    for (int k = 0; k <= d; ++k)
+        for (int a = 0; a < d; ++a) x[k][a] = xv[k * d + a];
+    double b[4];
+    p1_element_real(d, x, kappa, c, sigma, LOAD_NONE, 0.0, NULL, NULL, A, b, NULL);
+    return FO_OK;
+}
+
+/* sigma: NULL (kappa I) or 36 doubles; poly: 10 doubles when load == LOAD_POLY2 */
+int fo_assemble_p1_general(int d, int64_t n_nodes, int64_t n_elems, const double *coords,
+                           const int32_t *conn, const double *kappa, double c,
+                           const double *sigma, int load, const double *load_const,
+                           const double *poly, const int64_t *rowptr, const int32_t *colind,
+                           double *values, double *rhs, double *abs_values, double *abs_rhs)
 {
     if (d != 2 && d != 3) return FO_ERR_ARG;
+    if (load == LOAD_POLY2 && !poly) return FO_ERR_ARG;
     rule_t rule;
     if (p1_rule(d, &rule)) return FO_ERR_RULE;
     int64_t nnz = rowptr[n_nodes];
@@ -528,7 +672,7 @@ int fo_assemble_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords
             v[k] = conn[k * n_elems + e];
             for (int a = 0; a < d; ++a) x[k][a] = coords[a * n_nodes + v[k]];
         }
-        p1_element_real(d, x, kappa[e], c, load, fconst, &rule, A, b, NULL);
+        p1_element_real(d, x, kappa[e], c, sigma, load, fconst, poly, &rule, A, b, NULL);
         for (int i = 0; i < np; ++i) {
             for (int j = 0; j < np; ++j) {
                 int64_t s = find_slot(rowptr, colind, v[i], v[j]);
@@ -543,24 +687,45 @@ int fo_assemble_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords
     return FO_OK;
 }
 
+int fo_assemble_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords,
+                   const int32_t *conn, const double *kappa, double c, int load,
+                   const double *load_const, const int64_t *rowptr, const int32_t *colind,
+                   double *values, double *rhs, double *abs_values, double *abs_rhs)
+{
+    if (load == LOAD_POLY2) return FO_ERR_ARG;
+    return fo_assemble_p1_general(d, n_nodes, n_elems, coords, conn, kappa, c, NULL, load,
+                                  load_const, NULL, rowptr, colind, values, rhs, abs_values,
+                                  abs_rhs);
+}
+
 /* Complex version of the P1 element functional
  *   L_e(x) = sum_ij Gb_ij A_ij(x) + sum_i gb_i b_i(x),
  * with |det J| continued analytically as det * sign(Re det). */
-static cplx p1_local_L_c(int d, cplx x[4][3], double kappa, double c, int load, double fconst,
-                         const rule_t *rule, const double *Gb, const double *gb)
+static cplx p1_local_L_c(int d, cplx x[4][3], double kappa, double c, const double *sig,
+                         int load, double fconst, const double *poly, const rule_t *rule,
+                         const double *Gb, const double *gb)
 {
     cplx B[4][3];
     cplx det = geom_cplx(d, x, B);
     cplx vol = det * (creal(det) > 0 ? 1.0 : -1.0) / factorial(d);
     int np = d + 1;
+    cplx S[3][3];
+    if (sig) sigma_mean_cplx(d, x, sig, S);
     cplx L = 0.0;
     for (int i = 0; i < np; ++i)
         for (int j = 0; j < np; ++j) {
             cplx g = 0.0;
-            for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
+            if (sig) {
+                for (int a = 0; a < d; ++a)
+                    for (int b = 0; b < d; ++b) g += B[i][a] * S[a][b] * B[j][b];
+            } else {
+                for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
+            }
             L += Gb[i * np + j] * (kappa * vol * g + c * vol * mass_p1_ref(d, i, j));
         }
-    if (load == LOAD_CONST) {
+    if (load == LOAD_POLY2) {
+        for (int i = 0; i < np; ++i) L += gb[i] * vol * poly2_load_cplx(d, x, poly, i);
+    } else if (load == LOAD_CONST) {
         for (int i = 0; i < np; ++i) L += gb[i] * fconst * vol / (double)(d + 1);
     } else if (load == LOAD_SINPROD) {
         for (int q = 0; q < rule->n; ++q) {
@@ -577,17 +742,19 @@ static cplx p1_local_L_c(int d, cplx x[4][3], double kappa, double c, int load, 
 
 #define CSTEP 1e-30
 
-/* dL/dkappa_e = <Gbar_e, |T| grad l grad l^T> (L is linear in kappa);
+/* dL/dkappa_e = <Gbar_e, |T| grad l S grad l^T> (L is linear in kappa; S = I without sigma);
  * dL/dx by complex step of the element functional, scattered to nodes.
  * abs_dcoords[a][n] accumulates, per node, the largest |dL_e/dx| entry of every element
  * holding n (an element-level magnitude for the comparison tolerance). */
-int fo_backward_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords,
-                   const int32_t *conn, const double *kappa, double c, int load,
-                   const double *load_const, const int64_t *rowptr, const int32_t *colind,
-                   const double *Gbar, const double *gbar, double *dkappa, double *abs_dkappa,
-                   double *dcoords, double *abs_dcoords)
+int fo_backward_p1_general(int d, int64_t n_nodes, int64_t n_elems, const double *coords,
+                           const int32_t *conn, const double *kappa, double c,
+                           const double *sigma, int load, const double *load_const,
+                           const double *poly, const int64_t *rowptr, const int32_t *colind,
+                           const double *Gbar, const double *gbar, double *dkappa,
+                           double *abs_dkappa, double *dcoords, double *abs_dcoords)
 {
     if (d != 2 && d != 3) return FO_ERR_ARG;
+    if (load == LOAD_POLY2 && !poly) return FO_ERR_ARG;
     rule_t rule;
     if (p1_rule(d, &rule)) return FO_ERR_RULE;
     int np = d + 1;
@@ -610,13 +777,19 @@ int fo_backward_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords
             gb[i] = gbar ? gbar[v[i]] : 0.0;
         }
         if (dkappa || abs_dkappa) {
-            double B[4][3];
+            double B[4][3], S[3][3];
             double vol = fabs(geom_real(d, x, B)) / factorial(d);
+            if (sigma) sigma_mean_real(d, x, sigma, S);
             double acc = 0.0, aacc = 0.0;
             for (int i = 0; i < np; ++i)
                 for (int j = 0; j < np; ++j) {
                     double g = 0.0;
-                    for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
+                    if (sigma) {
+                        for (int a = 0; a < d; ++a)
+                            for (int b = 0; b < d; ++b) g += B[i][a] * S[a][b] * B[j][b];
+                    } else {
+                        for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
+                    }
                     acc += Gb[i * np + j] * vol * g;
                     aacc += fabs(Gb[i * np + j] * vol * g);
                 }
@@ -631,7 +804,8 @@ int fo_backward_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords
                     for (int kk = 0; kk < np; ++kk)
                         for (int aa = 0; aa < d; ++aa) xc[kk][aa] = x[kk][aa];
                     xc[k][a] += I * CSTEP;
-                    cplx L = p1_local_L_c(d, xc, kappa[e], c, load, fconst, &rule, Gb, gb);
+                    cplx L = p1_local_L_c(d, xc, kappa[e], c, sigma, load, fconst, poly, &rule,
+                                          Gb, gb);
                     grad[k][a] = cimag(L) / CSTEP;
                     if (fabs(grad[k][a]) > gmax) gmax = fabs(grad[k][a]);
                 }
@@ -643,6 +817,18 @@ int fo_backward_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords
         }
     }
     return FO_OK;
+}
+
+int fo_backward_p1(int d, int64_t n_nodes, int64_t n_elems, const double *coords,
+                   const int32_t *conn, const double *kappa, double c, int load,
+                   const double *load_const, const int64_t *rowptr, const int32_t *colind,
+                   const double *Gbar, const double *gbar, double *dkappa, double *abs_dkappa,
+                   double *dcoords, double *abs_dcoords)
+{
+    if (load == LOAD_POLY2) return FO_ERR_ARG;
+    return fo_backward_p1_general(d, n_nodes, n_elems, coords, conn, kappa, c, NULL, load,
+                                  load_const, NULL, rowptr, colind, Gbar, gbar, dkappa,
+                                  abs_dkappa, dcoords, abs_dcoords);
 }
 
 /* ------------------------------------------------------------------------------------
