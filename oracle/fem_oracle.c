@@ -577,10 +577,17 @@ static cplx poly2_load_cplx(int d, cplx x[4][3], const double *p, int i)
     return t;
 }
 
-/* sigma == NULL: the identity (kappa I); poly: the LOAD_POLY2 coefficients */
+/* sigma == NULL: the identity (kappa I); poly: the LOAD_POLY2 coefficients.
+ * Aabs, babs (optional): the magnitude each entry's arithmetic works at, for the
+ * comparison tolerance.  It is |A_ij|, |b_i| for the identity form and the other loads.
+ * A sigma entry sum_ab B_ia S_ab B_jb can cancel far below its terms (a rotation part
+ * meets nearly parallel gradients), and so can a quadratic load; there the magnitude is
+ * the same formula over absolute values (|B|, |S0| + sum_a |S_a| |x|, |p|, |x|), the
+ * scale of the rounding error of any evaluation order. */
 static void p1_element_real(int d, const double x[4][3], double kappa, double c,
                             const double *sig, int load, double fconst, const double *poly,
-                            const rule_t *rule, double A[16], double bvec[4], double *vol_out)
+                            const rule_t *rule, double A[16], double bvec[4], double *vol_out,
+                            double *Aabs, double *babs)
 {
     double B[4][3];
     double det = geom_real(d, x, B);
@@ -598,10 +605,37 @@ static void p1_element_real(int d, const double x[4][3], double kappa, double c,
                 for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
             }
             A[i * np + j] = kappa * vol * g + c * vol * mass_p1_ref(d, i, j);
+            if (Aabs) Aabs[i * np + j] = fabs(A[i * np + j]);
         }
+    if (sig && Aabs) {
+        double xa[4][3] = {{0}}, m[3], Sm[3][3];
+        for (int k = 0; k < np; ++k)
+            for (int a = 0; a < d; ++a) xa[k][a] = fabs(x[k][a]);
+        mean_coords_real(d, xa, m);
+        for (int r = 0; r < d; ++r)
+            for (int q = 0; q < d; ++q) {
+                double v = fabs(sig[r * 3 + q]);
+                for (int a = 0; a < d; ++a) v += fabs(sig[(1 + a) * 9 + r * 3 + q]) * m[a];
+                Sm[r][q] = v;
+            }
+        for (int i = 0; i < np; ++i)
+            for (int j = 0; j < np; ++j) {
+                double g = 0.0;
+                for (int a = 0; a < d; ++a)
+                    for (int b = 0; b < d; ++b) g += fabs(B[i][a]) * Sm[a][b] * fabs(B[j][b]);
+                Aabs[i * np + j] = fabs(kappa) * vol * g + fabs(c) * vol * mass_p1_ref(d, i, j);
+            }
+    }
     for (int i = 0; i < np; ++i) bvec[i] = 0.0;
     if (load == LOAD_POLY2) {
-        for (int i = 0; i < np; ++i) bvec[i] = vol * poly2_load_real(d, x, poly, i);
+        double xa[4][3] = {{0}}, pa[10];
+        for (int k = 0; k < np; ++k)
+            for (int a = 0; a < d; ++a) xa[k][a] = fabs(x[k][a]);
+        for (int k = 0; k < 10; ++k) pa[k] = fabs(poly[k]);
+        for (int i = 0; i < np; ++i) {
+            bvec[i] = vol * poly2_load_real(d, x, poly, i);
+            if (babs) babs[i] = vol * poly2_load_real(d, xa, pa, i);
+        }
     } else if (load == LOAD_CONST) {
         for (int i = 0; i < np; ++i) bvec[i] = fconst * vol / (double)(d + 1);
     } else if (load == LOAD_SINPROD) {
@@ -614,6 +648,8 @@ static void p1_element_real(int d, const double x[4][3], double kappa, double c,
             for (int i = 0; i < np; ++i) bvec[i] += vol * rule->w[q] * fq * lam[i];
         }
     }
+    if (babs && load != LOAD_POLY2)
+        for (int i = 0; i < np; ++i) babs[i] = fabs(bvec[i]);
     if (vol_out) *vol_out = vol;
 }
 
@@ -630,7 +666,7 @@ int fo_element_p1(int d, const double *xv, double kappa, double c, double *A)
     for (int k = 0; k <= d; ++k)
         for (int a = 0; a < d; ++a) x[k][a] = xv[k * d + a];
     double b[4];
-    p1_element_real(d, x, kappa, c, NULL, LOAD_NONE, 0.0, NULL, NULL, A, b, NULL);
+    p1_element_real(d, x, kappa, c, NULL, LOAD_NONE, 0.0, NULL, NULL, A, b, NULL, NULL, NULL);
     return FO_OK;
 }
 
@@ -643,7 +679,8 @@ int fo_element_p1_sigma(int d, const double *xv, double kappa, double c, const d
     for (int k = 0; k <= d; ++k)
         for (int a = 0; a < d; ++a) x[k][a] = xv[k * d + a];
     double b[4];
-    p1_element_real(d, x, kappa, c, sigma, LOAD_NONE, 0.0, NULL, NULL, A, b, NULL);
+    p1_element_real(d, x, kappa, c, sigma, LOAD_NONE, 0.0, NULL, NULL, A, b, NULL, NULL,
+                    NULL);
     return FO_OK;
 }
 
@@ -666,22 +703,23 @@ int fo_assemble_p1_general(int d, int64_t n_nodes, int64_t n_elems, const double
     double fconst = load_const ? load_const[0] : 0.0;
     int np = d + 1;
     for (int64_t e = 0; e < n_elems; ++e) {
-        double x[4][3], A[16], b[4];
+        double x[4][3], A[16], b[4], Aa[16], ba[4];
         int32_t v[4];
         for (int k = 0; k < np; ++k) {
             v[k] = conn[k * n_elems + e];
             for (int a = 0; a < d; ++a) x[k][a] = coords[a * n_nodes + v[k]];
         }
-        p1_element_real(d, x, kappa[e], c, sigma, load, fconst, poly, &rule, A, b, NULL);
+        p1_element_real(d, x, kappa[e], c, sigma, load, fconst, poly, &rule, A, b, NULL, Aa,
+                        ba);
         for (int i = 0; i < np; ++i) {
             for (int j = 0; j < np; ++j) {
                 int64_t s = find_slot(rowptr, colind, v[i], v[j]);
                 if (s < 0) return FO_ERR_NOTFOUND;
                 if (values) values[s] += A[i * np + j];
-                if (abs_values) abs_values[s] += fabs(A[i * np + j]);
+                if (abs_values) abs_values[s] += Aa[i * np + j];
             }
             if (rhs) rhs[v[i]] += b[i];
-            if (abs_rhs) abs_rhs[v[i]] += fabs(b[i]);
+            if (abs_rhs) abs_rhs[v[i]] += ba[i];
         }
     }
     return FO_OK;
@@ -777,9 +815,12 @@ int fo_backward_p1_general(int d, int64_t n_nodes, int64_t n_elems, const double
             gb[i] = gbar ? gbar[v[i]] : 0.0;
         }
         if (dkappa || abs_dkappa) {
-            double B[4][3], S[3][3];
+            double B[4][3], S[3][3], A1[16], b1[4], Aa[16], ba[4];
             double vol = fabs(geom_real(d, x, B)) / factorial(d);
             if (sigma) sigma_mean_real(d, x, sigma, S);
+            /* magnitudes of the kappa part (kappa = 1, c = 0) */
+            p1_element_real(d, x, 1.0, 0.0, sigma, LOAD_NONE, 0.0, NULL, NULL, A1, b1, NULL, Aa,
+                            ba);
             double acc = 0.0, aacc = 0.0;
             for (int i = 0; i < np; ++i)
                 for (int j = 0; j < np; ++j) {
@@ -791,7 +832,8 @@ int fo_backward_p1_general(int d, int64_t n_nodes, int64_t n_elems, const double
                         for (int a = 0; a < d; ++a) g += B[i][a] * B[j][a];
                     }
                     acc += Gb[i * np + j] * vol * g;
-                    aacc += fabs(Gb[i * np + j] * vol * g);
+                    aacc += sigma ? fabs(Gb[i * np + j]) * Aa[i * np + j]
+                                  : fabs(Gb[i * np + j] * vol * g);
                 }
             if (dkappa) dkappa[e] = acc;
             if (abs_dkappa) abs_dkappa[e] = aacc;
