@@ -6,7 +6,9 @@
  *   Sec. 4.1, Eq. (1)-(3): -div(kappa grad u) + c u = f on a mesh of Lagrange P1
  *     triangles or tetrahedra, Neumann boundary (no row is modified); A_ij sums the
  *     element integrals of every element holding nodes i and j, b_i those of every
- *     element holding node i.
+ *     element holding node i.  With a matrix coefficient, -div(kappa sigma(x) grad u),
+ *     sigma affine in x and not necessarily symmetric, and a quadratic f: the worked
+ *     example of Sec. 4.2.
  *   Sec. 5 (sparse variant): A is stored row-compressed; each row keeps the columns of
  *     every node sharing an element with the row's node (the paper's gNbrNodeLen /
  *     gNbrNodeIdx lists, here CSR rowptr / colind).  Alg. 1's scatter of element
@@ -58,11 +60,20 @@ extern "C" {
 #define FEM_FORM_HELMHOLTZ 1  /* (kappa grad v, grad u) + c (v, u); P1; coef = kappa */
 #define FEM_FORM_ELASTICITY 2 /* (lam div v, div u) + (2 mu eps(v), eps(u)); P2 3D;
                                   coef = lambda, mu */
+#define FEM_FORM_HELMHOLTZ_SIGMA 3 /* (grad v, kappa sigma(x) grad u) + c (v, u); P1;
+                                       coef = kappa; sigma(x) = sigma[0] + sum_a x_a
+                                       sigma[1+a] (fem_form.sigma), any real matrices:
+                                       row i of the element matrix is the test function,
+                                       column j the trial function.  The integrand is
+                                       affine in x, so it is evaluated exactly at the
+                                       element centroid */
 
 /* ---- right-hand sides (v, f) ---- */
 #define FEM_LOAD_NONE 0    /* rhs untouched (may be NULL) */
 #define FEM_LOAD_CONST 1   /* f = load_const (scalar: [0]; elasticity: body force [0..2]) */
-#define FEM_LOAD_SINPROD 2 /* f = prod_a sin(pi x_a) (Helmholtz only), by quadrature */
+#define FEM_LOAD_SINPROD 2 /* f = prod_a sin(pi x_a) (scalar forms), by quadrature */
+#define FEM_LOAD_POLY2 3   /* f = quadratic polynomial in x (fem_form.load_poly; scalar
+                              forms), by a degree-5 rule: exact up to rounding */
 
 /* ---- flags ---- */
 #define FEM_SCATTER_ATOMIC 0x0u   /* scatter with device-scope FP64 atomic adds */
@@ -122,8 +133,13 @@ typedef struct {
 typedef struct {
     int32_t kind;          /* FEM_FORM_* */
     int32_t load;          /* FEM_LOAD_* */
-    double reaction;       /* c of Eq. (1) (lambda there); Helmholtz only */
+    double reaction;       /* c of Eq. (1) (lambda there); scalar forms only */
     double load_const[3];  /* FEM_LOAD_CONST values */
+    double sigma[4][9];    /* FEM_FORM_HELMHOLTZ_SIGMA: sigma(x) = sigma[0] + x sigma[1] +
+                              y sigma[2] + z sigma[3], each a row-major 3x3 matrix; in 2D
+                              the leading 2x2 blocks of sigma[0..2] are read */
+    double load_poly[10];  /* FEM_LOAD_POLY2: f = sum of load_poly[k] times 1, x, y, z,
+                              x^2, xy, xz, y^2, yz, z^2 (terms in z are zero in 2D) */
 } fem_form;
 
 typedef struct {

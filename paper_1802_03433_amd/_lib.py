@@ -24,7 +24,8 @@ ERRORS = {
 }
 FORM_HELMHOLTZ = 1
 FORM_ELASTICITY = 2
-LOAD = {"none": 0, "const": 1, "sinprod": 2}
+FORM_HELMHOLTZ_SIGMA = 3
+LOAD = {"none": 0, "const": 1, "sinprod": 2, "poly2": 3}
 SCATTER_ATOMIC = 0x0
 SCATTER_COLOURED = 0x1
 ACCUMULATE = 0x2
@@ -99,6 +100,8 @@ class fem_form(ctypes.Structure):
         ("load", ctypes.c_int32),
         ("reaction", ctypes.c_double),
         ("load_const", ctypes.c_double * 3),
+        ("sigma", (ctypes.c_double * 9) * 4),
+        ("load_poly", ctypes.c_double * 10),
     ]
 
 

@@ -127,23 +127,50 @@ class Mesh:
         return m
 
 
+_FORMS = {"helmholtz": L.FORM_HELMHOLTZ, "elasticity": L.FORM_ELASTICITY,
+          "helmholtz-sigma": L.FORM_HELMHOLTZ_SIGMA}
+
+
 @dataclass
 class Form:
-    """kind: "helmholtz" or "elasticity"; load: "none" | "const" | "sinprod"."""
+    """kind: "helmholtz", "helmholtz-sigma" or "elasticity";
+    load: "none" | "const" | "sinprod" | "poly2".
+    sigma ("helmholtz-sigma"): up to 4 matrices S0, S_x, S_y, S_z (each up to 3x3) with
+    sigma(x) = S0 + x S_x + y S_y + z S_z.
+    load_poly ("poly2"): coefficients of 1, x, y, z, x^2, xy, xz, y^2, yz, z^2."""
 
     kind: str = "helmholtz"
     load: str = "none"
     reaction: float = 1.0
     load_const: tuple = field(default=(0.0, 0.0, 0.0))
+    sigma: object = None
+    load_poly: object = None
+
+    @staticmethod
+    def paper_example() -> "Form":
+        """The worked example of Sec. 4.2: sigma = [[1, -x-y], [x+y, 1]], lambda = 1,
+        f = -2(x^2 + y^2) + 36 (2D P1)."""
+        rot = ((0.0, -1.0), (1.0, 0.0))
+        return Form("helmholtz-sigma", "poly2", reaction=1.0,
+                    sigma=(((1.0, 0.0), (0.0, 1.0)), rot, rot),
+                    load_poly=(36.0, 0, 0, 0, -2.0, 0, 0, -2.0, 0, 0))
 
     def cstruct(self) -> L.fem_form:
         f = L.fem_form()
-        f.kind = {"helmholtz": L.FORM_HELMHOLTZ, "elasticity": L.FORM_ELASTICITY}[self.kind]
+        f.kind = _FORMS[self.kind]
         f.load = L.LOAD[self.load]
         f.reaction = float(self.reaction)
         lc = list(self.load_const) + [0.0] * (3 - len(self.load_const))
         for i in range(3):
             f.load_const[i] = float(lc[i])
+        if self.sigma is not None:
+            for k, S in enumerate(self.sigma):
+                for r, row in enumerate(S):
+                    for c, v in enumerate(row):
+                        f.sigma[k][3 * r + c] = float(v)
+        if self.load_poly is not None:
+            for k, v in enumerate(self.load_poly):
+                f.load_poly[k] = float(v)
         return f
 
     @property

@@ -43,19 +43,20 @@ int check_same_mesh(const fem_pattern *p, const fem_mesh *m)
 int check_form(const fem_pattern *p, const fem_form *f)
 {
     if (!f) return fail(FEM_ERR_INVALID_ARG, "form is NULL");
-    if (f->load != FEM_LOAD_NONE && f->load != FEM_LOAD_CONST && f->load != FEM_LOAD_SINPROD)
+    if (f->load != FEM_LOAD_NONE && f->load != FEM_LOAD_CONST && f->load != FEM_LOAD_SINPROD &&
+        f->load != FEM_LOAD_POLY2)
         return fail(FEM_ERR_INVALID_ARG, "unknown load kind");
-    if (f->kind == FEM_FORM_HELMHOLTZ) {
+    if (f->kind == FEM_FORM_HELMHOLTZ || f->kind == FEM_FORM_HELMHOLTZ_SIGMA) {
         if (p->order != 1 || p->ncomp != 1)
-            return fail(FEM_ERR_UNSUPPORTED, "Helmholtz form is provided for scalar P1 meshes");
+            return fail(FEM_ERR_UNSUPPORTED, "Helmholtz forms are provided for scalar P1 meshes");
         return FEM_OK;
     }
     if (f->kind == FEM_FORM_ELASTICITY) {
         if (p->order != 2 || p->dim != 3 || p->ncomp != 3)
             return fail(FEM_ERR_UNSUPPORTED,
                         "elasticity is provided for P2 tetrahedra with a 3-component pattern");
-        if (f->load == FEM_LOAD_SINPROD)
-            return fail(FEM_ERR_UNSUPPORTED, "elasticity takes no sin-product load");
+        if (f->load == FEM_LOAD_SINPROD || f->load == FEM_LOAD_POLY2)
+            return fail(FEM_ERR_UNSUPPORTED, "elasticity takes a constant body force only");
         if (!p->has_tiles)
             return fail(FEM_ERR_UNSUPPORTED, "elasticity needs the tile plan (rows of at most 128 nodes)");
         return FEM_OK;

@@ -1,5 +1,6 @@
-// P1 Helmholtz assembly, -div(kappa grad u) + c u = f (Sec. 4.1, Eq. (1)-(3)), and its
-// adjoint, on triangles (D = 2) and tetrahedra (D = 3).
+// P1 scalar assembly, -div(kappa sigma grad u) + c u = f (Sec. 4.1, Eq. (1)-(3); sigma = I
+// or an affine matrix field), and its adjoint, on triangles (D = 2) and tetrahedra
+// (D = 3), one element per thread with no tile combining.
 //
 // One thread per element (Alg. 1 gives each element a block of threads, one per
 // quadrature point and local entry; on CDNA a 4x4 P1 element is too little work to split
@@ -8,14 +9,16 @@
 //   geometry    J[a][m] = x_{m+1,a} - x_{0,a},  det J,  J^{-1} by cofactors,
 //               vol = |det J| / D!
 //   gradients   B = Ghat J^{-1} (row i = grad lambda_i; Ghat rows: (-1,..,-1), e_1..e_D)
-//   stiffness   kappa vol B B^T   (the integrand is constant on an affine element, so the
-//               quadrature sum collapses to one evaluation; the rule's weights sum to 1)
+//   stiffness   kappa vol B S B^T (S = I, or sigma at the centroid: the integrand is
+//               affine on an affine element, so one evaluation is its exact integral)
 //   mass        c vol M, M_ij = sum_q w_q lam_i(q) lam_j(q)    (folded at compile time)
 //   load        b_i = vol sum_q w_q f(x_q) lam_i(q),  x_q = sum_k lam_k(q) x_k
+//   (the arithmetic is p1_element.h's, shared with the tile kernels)
 //   scatter     values[slot(e,i,j)] += A_ij, rhs[conn_i] += b_i  (Alg. 1, last step):
 //               device-scope FP64 atomics, or plain read-modify-write when the launch
 //               covers one colour (no two elements of a colour share a node).
 #include "fem_internal.h"
+#include "p1_element.h"
 #include "quadrature.h"
 
 namespace fem {
@@ -35,92 +38,11 @@ struct P1Args {
     int64_t E;            // stride of conn/slot
     int64_t begin, count; // positions [begin, begin+count)
     const double *kappa;
-    double c, fconst;
+    P1Form form;
     double *values, *rhs;
     int *err;
     bool accumulate_unused;
 };
-
-template <int D>
-struct Geom {
-    double x[D + 1][D];
-    double inv[D][D];  // inv[m][a] = d xi_m / d x_a
-    double B[D + 1][D];
-    double det, vol;
-};
-
-template <int D>
-__device__ __forceinline__ void geometry(Geom<D> &g)
-{
-    double J[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int m = 0; m < D; ++m) J[a][m] = g.x[m + 1][a] - g.x[0][a];
-    if constexpr (D == 2) {
-        g.det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        double r = 1.0 / g.det;
-        g.inv[0][0] = J[1][1] * r;
-        g.inv[0][1] = -J[0][1] * r;
-        g.inv[1][0] = -J[1][0] * r;
-        g.inv[1][1] = J[0][0] * r;
-        g.vol = 0.5 * fabs(g.det);
-    } else {
-        // cofactors C[a][m] of J; inv[m][a] = C[a][m] / det
-        double C00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        double C01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        double C02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        double C10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-        double C11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-        double C12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-        double C20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-        double C21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-        double C22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        g.det = J[0][0] * C00 + J[0][1] * C01 + J[0][2] * C02;
-        double r = 1.0 / g.det;
-        g.inv[0][0] = C00 * r;
-        g.inv[1][0] = C01 * r;
-        g.inv[2][0] = C02 * r;
-        g.inv[0][1] = C10 * r;
-        g.inv[1][1] = C11 * r;
-        g.inv[2][1] = C12 * r;
-        g.inv[0][2] = C20 * r;
-        g.inv[1][2] = C21 * r;
-        g.inv[2][2] = C22 * r;
-        g.vol = fabs(g.det) * (1.0 / 6.0);
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < D; ++m) {
-            g.B[m + 1][a] = g.inv[m][a];
-            s += g.inv[m][a];
-        }
-        g.B[0][a] = -s;
-    }
-}
-
-template <int D>
-__device__ __forceinline__ void sinprod(const double *xq, double &f)
-{
-    f = 1.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) f *= fem_sinpi(xq[a]);
-}
-
-template <int D>
-__device__ __forceinline__ void quad_point(const Geom<D> &g, int q, double *xq)
-{
-    using R = quad::P1Rule<D>;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k <= D; ++k) s += R::lam(q, k) * g.x[k][a];
-        xq[a] = s;
-    }
-}
 
 __device__ __forceinline__ void scatter_add(double *p, double v, int mode)
 {
@@ -128,18 +50,17 @@ __device__ __forceinline__ void scatter_add(double *p, double v, int mode)
     else *p += v;
 }
 
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 __global__ __launch_bounds__(kThreads) void k_p1_fwd(P1Args a)
 {
     constexpr int NP = D + 1;
-    using R = quad::P1Rule<D>;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t t = blk * kThreads + threadIdx.x;
     if (t >= a.count) return;
     const int64_t pos = a.begin + t;
     const int64_t e = (MODE == kColoured) ? (int64_t)a.perm[pos] : pos;
 
-    Geom<D> g;
+    Elem<D> g;
     int32_t v[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) v[k] = a.conn[k * a.E + pos];
@@ -147,22 +68,9 @@ __global__ __launch_bounds__(kThreads) void k_p1_fwd(P1Args a)
     for (int k = 0; k < NP; ++k)
 #pragma unroll
         for (int d = 0; d < D; ++d) g.x[k][d] = a.coords[d * a.N + v[k]];
-    geometry<D>(g);
+    double A[NP][NP], b[NP];
+    p1_local<D, FORM, LOAD>(a.form, g, a.kappa[e], A, b);
     if (a.err && g.det == 0.0) atomicOr(a.err, 1);
-
-    const double kv = a.kappa[e] * g.vol;
-    const double cv = a.c * g.vol;
-    double A[NP][NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int j = i; j < NP; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) s += g.B[i][d] * g.B[j][d];
-            A[i][j] = kv * s + cv * quad::p1_mass<D>(i, j);
-            A[j][i] = A[i][j];
-        }
 #pragma unroll
     for (int i = 0; i < NP; ++i)
 #pragma unroll
@@ -170,37 +78,13 @@ __global__ __launch_bounds__(kThreads) void k_p1_fwd(P1Args a)
             int32_t s = a.slot[(int64_t)(i * NP + j) * a.E + pos];
             scatter_add(a.values + s, A[i][j], MODE);
         }
-
     if constexpr (LOAD != FEM_LOAD_NONE) {
-        double b[NP];
-#pragma unroll
-        for (int i = 0; i < NP; ++i) b[i] = 0.0;
-#pragma unroll
-        for (int q = 0; q < R::nq; ++q) {
-            double f;
-            if constexpr (LOAD == FEM_LOAD_SINPROD) {
-                double xq[D];
-                quad_point<D>(g, q, xq);
-                sinprod<D>(xq, f);
-            } else {
-                f = a.fconst;
-            }
-            const double wf = g.vol * R::w(q) * f;
-#pragma unroll
-            for (int i = 0; i < NP; ++i) b[i] += wf * R::lam(q, i);
-        }
 #pragma unroll
         for (int i = 0; i < NP; ++i) scatter_add(a.rhs + v[i], b[i], MODE);
     }
 }
 
-// ---- adjoint --------------------------------------------------------------------------
-// For L = <Gbar, values> + <gbar, rhs>, per element (S = Gbar_e + Gbar_e^T, s = <Gbar_e, BB^T>,
-// T = B^T S B, M the mass table, p_q = sum_i gbar_i lam_i(q)):
-//   dL/dkappa_e = vol s
-//   Jbar = vol [ (kappa s + c <Gbar_e, M> + sum_q w_q p_q f_q) I - kappa T ] J^{-T}
-//   xbar_{m+1} = Jbar[:, m],  xbar_0 = -sum_m Jbar[:, m]
-//   plus, through x_q:  xbar_k += vol sum_q w_q p_q lam_k(q) grad f(x_q).
+// ---- adjoint (formulas in p1_element.h) ---------------------------------------------
 struct P1BwdArgs {
     P1Args f;
     const double *gvalues, *grhs;
@@ -208,11 +92,10 @@ struct P1BwdArgs {
     bool accumulate;
 };
 
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 __global__ __launch_bounds__(kThreads) void k_p1_bwd(P1BwdArgs b)
 {
     constexpr int NP = D + 1;
-    using R = quad::P1Rule<D>;
     const P1Args &a = b.f;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t t = blk * kThreads + threadIdx.x;
@@ -220,7 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_p1_bwd(P1BwdArgs b)
     const int64_t pos = a.begin + t;
     const int64_t e = (MODE == kColoured) ? (int64_t)a.perm[pos] : pos;
 
-    Geom<D> g;
+    Elem<D> g;
     int32_t v[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) v[k] = a.conn[k * a.E + pos];
@@ -228,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_p1_bwd(P1BwdArgs b)
     for (int k = 0; k < NP; ++k)
 #pragma unroll
         for (int d = 0; d < D; ++d) g.x[k][d] = a.coords[d * a.N + v[k]];
-    geometry<D>(g);
+    elem_geometry<D>(g);
 
     double G[NP][NP];
 #pragma unroll
@@ -236,18 +119,8 @@ __global__ __launch_bounds__(kThreads) void k_p1_bwd(P1BwdArgs b)
 #pragma unroll
         for (int j = 0; j < NP; ++j)
             G[i][j] = b.gvalues ? b.gvalues[a.slot[(int64_t)(i * NP + j) * a.E + pos]] : 0.0;
-
-    double s = 0.0, msum = 0.0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            double bb = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) bb += g.B[i][d] * g.B[j][d];
-            s += G[i][j] * bb;
-            msum += G[i][j] * quad::p1_mass<D>(i, j);
-        }
+    double S[D][D], M[D][D], s, msum;
+    p1_adj_scalars<D, FORM>(a.form, g, G, S, M, s, msum);
     if (b.gkappa) {
         double dk = g.vol * s;
         if (b.accumulate) b.gkappa[e] += dk;
@@ -255,98 +128,33 @@ __global__ __launch_bounds__(kThreads) void k_p1_bwd(P1BwdArgs b)
     }
     if (!b.gcoords) return;
 
-    const double kap = a.kappa[e];
-    double xbar[NP][D];
+    double gb[NP], xbar[NP][D];
 #pragma unroll
-    for (int k = 0; k < NP; ++k)
-#pragma unroll
-        for (int d = 0; d < D; ++d) xbar[k][d] = 0.0;
-
-    double lterm = 0.0;
-    if constexpr (LOAD != FEM_LOAD_NONE) {
-        double gb[NP];
-#pragma unroll
-        for (int i = 0; i < NP; ++i) gb[i] = b.grhs ? b.grhs[v[i]] : 0.0;
-#pragma unroll
-        for (int q = 0; q < R::nq; ++q) {
-            double p = 0.0;
-#pragma unroll
-            for (int i = 0; i < NP; ++i) p += gb[i] * R::lam(q, i);
-            double f;
-            if constexpr (LOAD == FEM_LOAD_SINPROD) {
-                double xq[D], sn[D], cs[D];
-                quad_point<D>(g, q, xq);
-#pragma unroll
-                for (int d = 0; d < D; ++d) fem_sincospi(xq[d], &sn[d], &cs[d]);
-                f = 1.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) f *= sn[d];
-                const double wp = g.vol * R::w(q) * p;
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    double df = M_PI * cs[d];
-#pragma unroll
-                    for (int d2 = 0; d2 < D; ++d2)
-                        if (d2 != d) df *= sn[d2];
-#pragma unroll
-                    for (int k = 0; k < NP; ++k) xbar[k][d] += wp * R::lam(q, k) * df;
-                }
-            } else {
-                f = a.fconst;
-            }
-            lterm += R::w(q) * p * f;
-        }
-    }
-
-    // T = B^T (G + G^T) B
-    double T[D][D];
-#pragma unroll
-    for (int d1 = 0; d1 < D; ++d1)
-#pragma unroll
-        for (int d2 = 0; d2 < D; ++d2) {
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i < NP; ++i)
-#pragma unroll
-                for (int j = 0; j < NP; ++j) acc += g.B[i][d1] * (G[i][j] + G[j][i]) * g.B[j][d2];
-            T[d1][d2] = acc;
-        }
-    const double scal = kap * s + a.c * msum + lterm;
-#pragma unroll
-    for (int d1 = 0; d1 < D; ++d1)
-#pragma unroll
-        for (int m = 0; m < D; ++m) {
-            double jb = 0.0;
-#pragma unroll
-            for (int d2 = 0; d2 < D; ++d2)
-                jb += ((d1 == d2 ? scal : 0.0) - kap * T[d1][d2]) * g.inv[m][d2];
-            jb *= g.vol;
-            xbar[m + 1][d1] += jb;
-            xbar[0][d1] -= jb;
-        }
+    for (int i = 0; i < NP; ++i) gb[i] = (LOAD != FEM_LOAD_NONE && b.grhs) ? b.grhs[v[i]] : 0.0;
+    p1_adj_coords<D, FORM, LOAD>(a.form, g, a.kappa[e], G, S, M, gb, s, msum, xbar);
 #pragma unroll
     for (int k = 0; k < NP; ++k)
 #pragma unroll
         for (int d = 0; d < D; ++d) scatter_add(b.gcoords + d * a.N + v[k], xbar[k][d], MODE);
 }
 
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 void launch_fwd(const P1Args &a, hipStream_t s)
 {
     if (a.count <= 0) return;
-    hipLaunchKernelGGL((k_p1_fwd<D, LOAD, MODE>), dim3(grid_for(a.count, kThreads)), dim3(kThreads),
+    hipLaunchKernelGGL((k_p1_fwd<D, LOAD, MODE, FORM>), dim3(grid_for(a.count, kThreads)), dim3(kThreads),
                        0, s, a);
 }
 
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 void launch_bwd(const P1BwdArgs &b, hipStream_t s)
 {
     if (b.f.count <= 0) return;
-    hipLaunchKernelGGL((k_p1_bwd<D, LOAD, MODE>), dim3(grid_for(b.f.count, kThreads)),
+    hipLaunchKernelGGL((k_p1_bwd<D, LOAD, MODE, FORM>), dim3(grid_for(b.f.count, kThreads)),
                        dim3(kThreads), 0, s, b);
 }
 
-template <int D, int LOAD>
+template <int D, int LOAD, int FORM>
 void run_fwd(const fem_pattern *p, P1Args a, bool coloured, hipStream_t s)
 {
     if (!coloured) {
@@ -355,7 +163,7 @@ void run_fwd(const fem_pattern *p, P1Args a, bool coloured, hipStream_t s)
         a.perm = nullptr;
         a.begin = 0;
         a.count = p->n_elems;
-        launch_fwd<D, LOAD, kAtomic>(a, s);
+        launch_fwd<D, LOAD, kAtomic, FORM>(a, s);
         return;
     }
     a.conn = p->conn_perm;
@@ -364,11 +172,11 @@ void run_fwd(const fem_pattern *p, P1Args a, bool coloured, hipStream_t s)
     for (int c = 0; c < p->n_colours; ++c) {
         a.begin = p->colour_ptr[c];
         a.count = p->colour_ptr[c + 1] - p->colour_ptr[c];
-        launch_fwd<D, LOAD, kColoured>(a, s);
+        launch_fwd<D, LOAD, kColoured, FORM>(a, s);
     }
 }
 
-template <int D, int LOAD>
+template <int D, int LOAD, int FORM>
 void run_bwd(const fem_pattern *p, P1BwdArgs b, bool coloured, hipStream_t s)
 {
     if (!coloured) {
@@ -376,7 +184,7 @@ void run_bwd(const fem_pattern *p, P1BwdArgs b, bool coloured, hipStream_t s)
         b.f.perm = nullptr;
         b.f.begin = 0;
         b.f.count = p->n_elems;
-        launch_bwd<D, LOAD, kAtomic>(b, s);
+        launch_bwd<D, LOAD, kAtomic, FORM>(b, s);
         return;
     }
     b.f.conn = p->conn_perm;
@@ -385,28 +193,48 @@ void run_bwd(const fem_pattern *p, P1BwdArgs b, bool coloured, hipStream_t s)
     for (int c = 0; c < p->n_colours; ++c) {
         b.f.begin = p->colour_ptr[c];
         b.f.count = p->colour_ptr[c + 1] - p->colour_ptr[c];
-        launch_bwd<D, LOAD, kColoured>(b, s);
+        launch_bwd<D, LOAD, kColoured, FORM>(b, s);
+    }
+}
+
+template <int D, int FORM>
+void dispatch_fwd_load(const fem_pattern *p, const P1Args &a, int load, bool coloured, hipStream_t s)
+{
+    switch (load) {
+    case FEM_LOAD_NONE: run_fwd<D, FEM_LOAD_NONE, FORM>(p, a, coloured, s); break;
+    case FEM_LOAD_CONST: run_fwd<D, FEM_LOAD_CONST, FORM>(p, a, coloured, s); break;
+    case FEM_LOAD_POLY2: run_fwd<D, FEM_LOAD_POLY2, FORM>(p, a, coloured, s); break;
+    default: run_fwd<D, FEM_LOAD_SINPROD, FORM>(p, a, coloured, s); break;
+    }
+}
+
+template <int D, int FORM>
+void dispatch_bwd_load(const fem_pattern *p, const P1BwdArgs &b, int load, bool coloured, hipStream_t s)
+{
+    switch (load) {
+    case FEM_LOAD_NONE: run_bwd<D, FEM_LOAD_NONE, FORM>(p, b, coloured, s); break;
+    case FEM_LOAD_CONST: run_bwd<D, FEM_LOAD_CONST, FORM>(p, b, coloured, s); break;
+    case FEM_LOAD_POLY2: run_bwd<D, FEM_LOAD_POLY2, FORM>(p, b, coloured, s); break;
+    default: run_bwd<D, FEM_LOAD_SINPROD, FORM>(p, b, coloured, s); break;
     }
 }
 
 template <int D>
-void dispatch_fwd(const fem_pattern *p, const P1Args &a, int load, bool coloured, hipStream_t s)
+void dispatch_fwd(const fem_pattern *p, const P1Args &a, int form, int load, bool coloured,
+                  hipStream_t s)
 {
-    switch (load) {
-    case FEM_LOAD_NONE: run_fwd<D, FEM_LOAD_NONE>(p, a, coloured, s); break;
-    case FEM_LOAD_CONST: run_fwd<D, FEM_LOAD_CONST>(p, a, coloured, s); break;
-    default: run_fwd<D, FEM_LOAD_SINPROD>(p, a, coloured, s); break;
-    }
+    if (form == FEM_FORM_HELMHOLTZ_SIGMA)
+        dispatch_fwd_load<D, FEM_FORM_HELMHOLTZ_SIGMA>(p, a, load, coloured, s);
+    else dispatch_fwd_load<D, FEM_FORM_HELMHOLTZ>(p, a, load, coloured, s);
 }
 
 template <int D>
-void dispatch_bwd(const fem_pattern *p, const P1BwdArgs &b, int load, bool coloured, hipStream_t s)
+void dispatch_bwd(const fem_pattern *p, const P1BwdArgs &b, int form, int load, bool coloured,
+                  hipStream_t s)
 {
-    switch (load) {
-    case FEM_LOAD_NONE: run_bwd<D, FEM_LOAD_NONE>(p, b, coloured, s); break;
-    case FEM_LOAD_CONST: run_bwd<D, FEM_LOAD_CONST>(p, b, coloured, s); break;
-    default: run_bwd<D, FEM_LOAD_SINPROD>(p, b, coloured, s); break;
-    }
+    if (form == FEM_FORM_HELMHOLTZ_SIGMA)
+        dispatch_bwd_load<D, FEM_FORM_HELMHOLTZ_SIGMA>(p, b, load, coloured, s);
+    else dispatch_bwd_load<D, FEM_FORM_HELMHOLTZ>(p, b, load, coloured, s);
 }
 
 __global__ void k_p1_validate(const double *__restrict__ coords, int64_t N,
@@ -460,8 +288,7 @@ int p1_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const
     a.conn = m->conn;
     a.E = m->n_elems;
     a.kappa = coef;
-    a.c = f->reaction;
-    a.fconst = f->load_const[0];
+    a.form = p1_form_of(f);
     a.values = values;
     a.rhs = rhs;
     int *d_err = nullptr;
@@ -472,8 +299,8 @@ int p1_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, const
     a.err = d_err;
     bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
     int load = rhs ? f->load : FEM_LOAD_NONE;
-    if (m->dim == 2) dispatch_fwd<2>(p, a, load, coloured, s);
-    else dispatch_fwd<3>(p, a, load, coloured, s);
+    if (m->dim == 2) dispatch_fwd<2>(p, a, f->kind, load, coloured, s);
+    else dispatch_fwd<3>(p, a, f->kind, load, coloured, s);
     FEM_HIP_TRY(hipGetLastError());
     if (d_err) {
         int h = 0;
@@ -495,8 +322,7 @@ int p1_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, cons
     b.f.conn = m->conn;
     b.f.E = m->n_elems;
     b.f.kappa = coef;
-    b.f.c = f->reaction;
-    b.f.fconst = f->load_const[0];
+    b.f.form = p1_form_of(f);
     b.gvalues = gvalues;
     b.grhs = grhs;
     b.gkappa = gcoef;
@@ -504,8 +330,8 @@ int p1_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, cons
     b.accumulate = (flags & FEM_ACCUMULATE) != 0;
     bool coloured = (flags & FEM_SCATTER_COLOURED) != 0;
     int load = grhs ? f->load : FEM_LOAD_NONE;
-    if (m->dim == 2) dispatch_bwd<2>(p, b, load, coloured, s);
-    else dispatch_bwd<3>(p, b, load, coloured, s);
+    if (m->dim == 2) dispatch_bwd<2>(p, b, f->kind, load, coloured, s);
+    else dispatch_bwd<3>(p, b, f->kind, load, coloured, s);
     FEM_HIP_TRY(hipGetLastError());
     return FEM_OK;
 }

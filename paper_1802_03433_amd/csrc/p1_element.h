@@ -1,0 +1,416 @@
+// Per-element arithmetic of the P1 scalar forms and of their adjoint, shared by the
+// tile-combined kernels (p1_tile.hip) and the per-element kernels (p1.hip).
+//
+// Forms (Sec. 4.1, Eq. (1)-(2)), on an affine triangle (D = 2) or tetrahedron (D = 3):
+//   FEM_FORM_HELMHOLTZ        A_ij = kappa vol grad l_i . grad l_j + c vol M_ij
+//   FEM_FORM_HELMHOLTZ_SIGMA  A_ij = kappa vol grad l_i . S grad l_j + c vol M_ij,
+//     S = sigma(x_c): sigma(x) = S0 + sum_a x_a S_a is affine, so its integral over the
+//     element is vol times its value at the centroid x_c (Sec. 4.2's example has
+//     sigma = [[1, -x-y], [x+y, 1]], not symmetric).  Row i is the test function l_i.
+// with M_ij = sum_q w_q l_i(q) l_j(q) (the reference mass table) and the load
+//   b_i = vol sum_q w_q f(x_q) l_i(q),  x_q = sum_k l_k(q) x_k,
+// by the degree-2 rule (constant and sin-product loads) or the degree-5 rule (quadratic
+// loads: the degree-3 integrand is then integrated exactly).
+//
+// Adjoint, for L = <Gbar, A> + <gbar, b> per element (Gbar_e the element's entries of the
+// upstream value gradient, p_q = sum_i gbar_i l_i(q), M = B^T Gbar_e B with B the rows
+// grad l_i, S = I for FEM_FORM_HELMHOLTZ):
+//   dL/dkappa_e = vol <S, M>
+//   Jbar = vol [ (kappa <S, M> + c <Gbar_e, M_ref> + sum_q w_q p_q f_q) I
+//                - kappa (M S^T + M^T S) ] J^{-T}         (J[a][m] = x_{m+1,a} - x_{0,a})
+//   xbar_{m+1} = Jbar[:, m],  xbar_0 = -sum_m Jbar[:, m]
+//   through x_q:   xbar_k += vol sum_q w_q p_q l_k(q) grad f(x_q)
+//   through x_c:   xbar_k[a] += kappa vol <S_a, M> / (D + 1)      (sigma form)
+#pragma once
+
+#include "fem_internal.h"
+#include "quadrature.h"
+
+namespace fem {
+
+// Per-call constants of a P1 form (from fem_form)
+struct P1Form {
+    double c;             // reaction
+    double fconst;        // FEM_LOAD_CONST
+    double sig[4][3][3];  // FEM_FORM_HELMHOLTZ_SIGMA: S0, S_x, S_y, S_z
+    double poly[10];      // FEM_LOAD_POLY2: 1, x, y, z, x^2, xy, xz, y^2, yz, z^2
+};
+
+inline P1Form p1_form_of(const fem_form *f)
+{
+    P1Form p{};
+    p.c = f->reaction;
+    p.fconst = f->load_const[0];
+    for (int k = 0; k < 4; ++k)
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) p.sig[k][r][q] = f->sigma[k][3 * r + q];
+    for (int k = 0; k < 10; ++k) p.poly[k] = f->load_poly[k];
+    return p;
+}
+
+template <int D>
+struct Elem {
+    double x[D + 1][D];
+    double inv[D][D];  // inv[m][a] = d xi_m / d x_a
+    double B[D + 1][D];
+    double det, vol;
+};
+
+// J[a][m] = x_{m+1,a} - x_{0,a}, det J, J^{-1} by cofactors, vol = |det J| / D!,
+// B = Ghat J^{-1} (row i = grad l_i; Ghat rows (-1,..,-1), e_1..e_D)
+template <int D>
+__device__ __forceinline__ void elem_geometry(Elem<D> &g)
+{
+    double J[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int m = 0; m < D; ++m) J[a][m] = g.x[m + 1][a] - g.x[0][a];
+    if constexpr (D == 2) {
+        g.det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        double r = 1.0 / g.det;
+        g.inv[0][0] = J[1][1] * r;
+        g.inv[0][1] = -J[0][1] * r;
+        g.inv[1][0] = -J[1][0] * r;
+        g.inv[1][1] = J[0][0] * r;
+        g.vol = 0.5 * fabs(g.det);
+    } else {
+        // cofactors C[a][m] of J; inv[m][a] = C[a][m] / det
+        double C00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        double C01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        double C02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        double C10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        double C11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        double C12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        double C20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        double C21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        double C22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        g.det = J[0][0] * C00 + J[0][1] * C01 + J[0][2] * C02;
+        double r = 1.0 / g.det;
+        g.inv[0][0] = C00 * r;
+        g.inv[1][0] = C01 * r;
+        g.inv[2][0] = C02 * r;
+        g.inv[0][1] = C10 * r;
+        g.inv[1][1] = C11 * r;
+        g.inv[2][1] = C12 * r;
+        g.inv[0][2] = C20 * r;
+        g.inv[1][2] = C21 * r;
+        g.inv[2][2] = C22 * r;
+        g.vol = fabs(g.det) * (1.0 / 6.0);
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            g.B[m + 1][a] = g.inv[m][a];
+            s += g.inv[m][a];
+        }
+        g.B[0][a] = -s;
+    }
+}
+
+// quadrature rule of each load
+template <int D, int LOAD>
+struct LoadRule {
+    using type = quad::P1Rule<D>;
+};
+template <>
+struct LoadRule<2, FEM_LOAD_POLY2> {
+    using type = quad::Tri7;
+};
+template <>
+struct LoadRule<3, FEM_LOAD_POLY2> {
+    using type = quad::Tet14;
+};
+
+template <int D, class R>
+__device__ __forceinline__ void qpoint(const Elem<D> &g, int q, double *xq)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k <= D; ++k) s += R::lam(q, k) * g.x[k][a];
+        xq[a] = s;
+    }
+}
+
+// the quadratic load and its gradient (z terms absent in 2D)
+template <int D>
+__device__ __forceinline__ double poly2(const double *p, const double *x)
+{
+    if constexpr (D == 2)
+        return p[0] + p[1] * x[0] + p[2] * x[1] + x[0] * (p[4] * x[0] + p[5] * x[1]) +
+               p[7] * x[1] * x[1];
+    else
+        return p[0] + p[1] * x[0] + p[2] * x[1] + p[3] * x[2] +
+               x[0] * (p[4] * x[0] + p[5] * x[1] + p[6] * x[2]) +
+               x[1] * (p[7] * x[1] + p[8] * x[2]) + p[9] * x[2] * x[2];
+}
+
+template <int D>
+__device__ __forceinline__ void poly2_grad(const double *p, const double *x, double *gr)
+{
+    if constexpr (D == 2) {
+        gr[0] = p[1] + 2.0 * p[4] * x[0] + p[5] * x[1];
+        gr[1] = p[2] + p[5] * x[0] + 2.0 * p[7] * x[1];
+    } else {
+        gr[0] = p[1] + 2.0 * p[4] * x[0] + p[5] * x[1] + p[6] * x[2];
+        gr[1] = p[2] + p[5] * x[0] + 2.0 * p[7] * x[1] + p[8] * x[2];
+        gr[2] = p[3] + p[6] * x[0] + p[8] * x[1] + 2.0 * p[9] * x[2];
+    }
+}
+
+// S = sigma(x_c), the element mean of the affine matrix field
+template <int D>
+__device__ __forceinline__ void sigma_bar(const P1Form &f, const Elem<D> &g, double S[D][D])
+{
+    double xc[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k <= D; ++k) s += g.x[k][a];
+        xc[a] = s * (1.0 / (D + 1));
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            double v = f.sig[0][r][q];
+#pragma unroll
+            for (int a = 0; a < D; ++a) v += f.sig[1 + a][r][q] * xc[a];
+            S[r][q] = v;
+        }
+}
+
+// Element matrix A and load vector bv from the vertex coordinates in g (Alg. 1's
+// per-element steps); also fills g's geometry.
+template <int D, int FORM, int LOAD>
+__device__ __forceinline__ void p1_local(const P1Form &f, Elem<D> &g, double kap,
+                                         double A[D + 1][D + 1], double bv[D + 1])
+{
+    constexpr int NP = D + 1;
+    elem_geometry<D>(g);
+    const double kv = kap * g.vol, cv = f.c * g.vol;
+    if constexpr (FORM == FEM_FORM_HELMHOLTZ_SIGMA) {
+        double S[D][D], C[NP][D];
+        sigma_bar<D>(f, g, S);
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) s += g.B[i][a] * S[a][b];
+                C[i][b] = s;
+            }
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b < D; ++b) s += C[i][b] * g.B[j][b];
+                A[i][j] = kv * s + cv * quad::p1_mass<D>(i, j);
+            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int j = i; j < NP; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) s += g.B[i][d] * g.B[j][d];
+                A[i][j] = kv * s + cv * quad::p1_mass<D>(i, j);
+                A[j][i] = A[i][j];
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) bv[i] = 0.0;
+    if constexpr (LOAD != FEM_LOAD_NONE) {
+        using R = typename LoadRule<D, LOAD>::type;
+#pragma unroll
+        for (int q = 0; q < R::nq; ++q) {
+            double fv;
+            if constexpr (LOAD == FEM_LOAD_SINPROD) {
+                double xq[D];
+                qpoint<D, R>(g, q, xq);
+                fv = 1.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) fv *= fem_sinpi(xq[d]);
+            } else if constexpr (LOAD == FEM_LOAD_POLY2) {
+                double xq[D];
+                qpoint<D, R>(g, q, xq);
+                fv = poly2<D>(f.poly, xq);
+            } else {
+                fv = f.fconst;
+            }
+            const double wf = g.vol * R::w(q) * fv;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) bv[i] += wf * R::lam(q, i);
+        }
+    }
+}
+
+// Adjoint, first part: s = <S, M> (= <Gbar_e, B S B^T>), msum = <Gbar_e, M_ref>, and for
+// the sigma form S and M = B^T Gbar_e B.  g's geometry must be filled.
+template <int D, int FORM>
+__device__ __forceinline__ void p1_adj_scalars(const P1Form &f, const Elem<D> &g,
+                                               const double G[D + 1][D + 1], double S[D][D],
+                                               double M[D][D], double &s, double &msum)
+{
+    constexpr int NP = D + 1;
+    s = 0.0;
+    msum = 0.0;
+    if constexpr (FORM == FEM_FORM_HELMHOLTZ_SIGMA) {
+        sigma_bar<D>(f, g, S);
+        double GB[NP][D];  // Gbar_e B
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                double t = 0.0;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) t += G[i][j] * g.B[j][b];
+                GB[i][b] = t;
+            }
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                double t = 0.0;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) t += g.B[i][a] * GB[i][b];
+                M[a][b] = t;
+                s += S[a][b] * t;
+            }
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) msum += G[i][j] * quad::p1_mass<D>(i, j);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                double bb = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) bb += g.B[i][d] * g.B[j][d];
+                s += G[i][j] * bb;
+                msum += G[i][j] * quad::p1_mass<D>(i, j);
+            }
+    }
+}
+
+// Adjoint, second part: the vertex gradients xbar of L_e (overwritten).  gb: the
+// element's upstream RHS gradient (read only with a load).
+template <int D, int FORM, int LOAD>
+__device__ __forceinline__ void p1_adj_coords(const P1Form &f, const Elem<D> &g, double kap,
+                                              const double G[D + 1][D + 1], const double S[D][D],
+                                              const double M[D][D], const double gb[D + 1],
+                                              double s, double msum, double xbar[D + 1][D])
+{
+    constexpr int NP = D + 1;
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int d = 0; d < D; ++d) xbar[k][d] = 0.0;
+    double lterm = 0.0;
+    if constexpr (LOAD != FEM_LOAD_NONE) {
+        using R = typename LoadRule<D, LOAD>::type;
+#pragma unroll
+        for (int q = 0; q < R::nq; ++q) {
+            double p = 0.0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) p += gb[i] * R::lam(q, i);
+            double fv;
+            if constexpr (LOAD == FEM_LOAD_SINPROD) {
+                double xq[D], sn[D], cs[D];
+                qpoint<D, R>(g, q, xq);
+#pragma unroll
+                for (int d = 0; d < D; ++d) fem_sincospi(xq[d], &sn[d], &cs[d]);
+                fv = 1.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) fv *= sn[d];
+                const double wp = g.vol * R::w(q) * p;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    double df = M_PI * cs[d];
+#pragma unroll
+                    for (int d2 = 0; d2 < D; ++d2)
+                        if (d2 != d) df *= sn[d2];
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) xbar[k][d] += wp * R::lam(q, k) * df;
+                }
+            } else if constexpr (LOAD == FEM_LOAD_POLY2) {
+                double xq[D], gr[D];
+                qpoint<D, R>(g, q, xq);
+                fv = poly2<D>(f.poly, xq);
+                poly2_grad<D>(f.poly, xq, gr);
+                const double wp = g.vol * R::w(q) * p;
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) xbar[k][d] += wp * R::lam(q, k) * gr[d];
+            } else {
+                fv = f.fconst;
+            }
+            lterm += R::w(q) * p * fv;
+        }
+    }
+    // T = B^T (G + G^T) B for the identity; M S^T + M^T S for sigma
+    double T[D][D];
+    if constexpr (FORM == FEM_FORM_HELMHOLTZ_SIGMA) {
+#pragma unroll
+        for (int d1 = 0; d1 < D; ++d1)
+#pragma unroll
+            for (int d2 = 0; d2 < D; ++d2) {
+                double acc = 0.0;
+#pragma unroll
+                for (int e = 0; e < D; ++e) acc += M[d1][e] * S[d2][e] + M[e][d1] * S[e][d2];
+                T[d1][d2] = acc;
+            }
+        // sigma's dependence on the centroid
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double t = 0.0;
+#pragma unroll
+            for (int r = 0; r < D; ++r)
+#pragma unroll
+                for (int q = 0; q < D; ++q) t += f.sig[1 + a][r][q] * M[r][q];
+            t *= kap * g.vol * (1.0 / NP);
+#pragma unroll
+            for (int k = 0; k < NP; ++k) xbar[k][a] += t;
+        }
+    } else {
+#pragma unroll
+        for (int d1 = 0; d1 < D; ++d1)
+#pragma unroll
+            for (int d2 = 0; d2 < D; ++d2) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < NP; ++i)
+#pragma unroll
+                    for (int j = 0; j < NP; ++j)
+                        acc += g.B[i][d1] * (G[i][j] + G[j][i]) * g.B[j][d2];
+                T[d1][d2] = acc;
+            }
+    }
+    const double scal = kap * s + f.c * msum + lterm;
+#pragma unroll
+    for (int d1 = 0; d1 < D; ++d1)
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            double jb = 0.0;
+#pragma unroll
+            for (int d2 = 0; d2 < D; ++d2)
+                jb += ((d1 == d2 ? scal : 0.0) - kap * T[d1][d2]) * g.inv[m][d2];
+            jb *= g.vol;
+            xbar[m + 1][d1] += jb;
+            xbar[0][d1] -= jb;
+        }
+}
+
+}  // namespace fem

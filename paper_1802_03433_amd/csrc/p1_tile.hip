@@ -16,6 +16,7 @@
 #include <cstring>
 
 #include "fem_internal.h"
+#include "p1_element.h"
 #include "quadrature.h"
 
 namespace fem {
@@ -42,7 +43,7 @@ struct TileArgs {
     const int32_t *pred_ptr, *pred;
     int32_t *flags, *counter, *err;  // ordered scatter: done flags, ticket counter, spin failure
     const double *kappa;
-    double c, fconst;
+    P1Form form;
     int nmax, smax;
     bool use_first;
     // forward
@@ -136,123 +137,9 @@ __device__ int stage_tile(const TileArgs &a, Lds<D> &L, int64_t tile, int nn, bo
     return ns;
 }
 
-template <int D>
-struct Elem {
-    double x[D + 1][D];
-    double inv[D][D];
-    double B[D + 1][D];
-    double det, vol;
-};
-
-template <int D>
-__device__ __forceinline__ void elem_geometry(Elem<D> &g)
-{
-    double J[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int m = 0; m < D; ++m) J[a][m] = g.x[m + 1][a] - g.x[0][a];
-    if constexpr (D == 2) {
-        g.det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        double r = 1.0 / g.det;
-        g.inv[0][0] = J[1][1] * r;
-        g.inv[0][1] = -J[0][1] * r;
-        g.inv[1][0] = -J[1][0] * r;
-        g.inv[1][1] = J[0][0] * r;
-        g.vol = 0.5 * fabs(g.det);
-    } else {
-        double C00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        double C01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        double C02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        double C10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-        double C11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-        double C12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-        double C20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-        double C21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-        double C22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        g.det = J[0][0] * C00 + J[0][1] * C01 + J[0][2] * C02;
-        double r = 1.0 / g.det;
-        g.inv[0][0] = C00 * r;
-        g.inv[1][0] = C01 * r;
-        g.inv[2][0] = C02 * r;
-        g.inv[0][1] = C10 * r;
-        g.inv[1][1] = C11 * r;
-        g.inv[2][1] = C12 * r;
-        g.inv[0][2] = C20 * r;
-        g.inv[1][2] = C21 * r;
-        g.inv[2][2] = C22 * r;
-        g.vol = fabs(g.det) * (1.0 / 6.0);
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < D; ++m) {
-            g.B[m + 1][a] = g.inv[m][a];
-            s += g.inv[m][a];
-        }
-        g.B[0][a] = -s;
-    }
-}
-
-template <int D>
-__device__ __forceinline__ void qpoint(const Elem<D> &g, int q, double *xq)
-{
-    using R = quad::P1Rule<D>;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k <= D; ++k) s += R::lam(q, k) * g.x[k][a];
-        xq[a] = s;
-    }
-}
-
-// Element matrix A (stiffness + mass, exact for affine elements) and load vector by the
-// rule, from the element's vertex coordinates (Alg. 1's per-element steps)
-template <int D, int LOAD>
-__device__ __forceinline__ void p1_local(const TileArgs &a, Elem<D> &g, double kap,
-                                         double A[D + 1][D + 1], double bv[D + 1])
-{
-    constexpr int NP = D + 1;
-    using R = quad::P1Rule<D>;
-    elem_geometry<D>(g);
-    const double kv = kap * g.vol, cv = a.c * g.vol;
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int j = i; j < NP; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) s += g.B[i][d] * g.B[j][d];
-            A[i][j] = kv * s + cv * quad::p1_mass<D>(i, j);
-            A[j][i] = A[i][j];
-        }
-#pragma unroll
-    for (int i = 0; i < NP; ++i) bv[i] = 0.0;
-    if constexpr (LOAD != FEM_LOAD_NONE) {
-#pragma unroll
-        for (int q = 0; q < R::nq; ++q) {
-            double f;
-            if constexpr (LOAD == FEM_LOAD_SINPROD) {
-                double xq[D];
-                qpoint<D>(g, q, xq);
-                f = 1.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) f *= fem_sinpi(xq[d]);
-            } else {
-                f = a.fconst;
-            }
-            const double wf = g.vol * R::w(q) * f;
-#pragma unroll
-            for (int i = 0; i < NP; ++i) bv[i] += wf * R::lam(q, i);
-        }
-    }
-}
-
 // One element of a staged tile: vertex coordinates from the tile's LDS, the local matrix
 // and load vector, and the tile-local slot index of each entry.
-template <int D, int LOAD>
+template <int D, int FORM, int LOAD>
 __device__ __forceinline__ void p1_element(const TileArgs &a, const double *xs, const uint64_t *rb,
                                            const int32_t *ust, uint64_t en, const uint32_t pr[D + 1],
                                            double kap, double A[D + 1][D + 1], double bv[D + 1],
@@ -266,7 +153,7 @@ __device__ __forceinline__ void p1_element(const TileArgs &a, const double *xs, 
 #pragma unroll
         for (int d = 0; d < D; ++d) g.x[k][d] = xs[d * a.nmax + ki[k]];
     }
-    p1_local<D, LOAD>(a, g, kap, A, bv);
+    p1_local<D, FORM, LOAD>(a.form, g, kap, A, bv);
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
         const uint64_t r = rb[ki[i]];
@@ -300,7 +187,7 @@ __device__ __forceinline__ unsigned long long fx_round(double v, int s)
     return (unsigned long long)(__double_as_longlong(ldexp(v, s) + magic) - 0x4338000000000000ll);
 }
 
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
 {
     constexpr int NP = D + 1;
@@ -327,7 +214,7 @@ __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
 
     double A[NP][NP], bv[NP];
     int ki[NP], li[NP][NP];
-    if (active) p1_element<D, LOAD>(a, L.xs, L.rb, L.ust, en, pr, kap, A, bv, ki, li);
+    if (active) p1_element<D, FORM, LOAD>(a, L.xs, L.rb, L.ust, en, pr, kap, A, bv, ki, li);
     if (MODE == kAtomic) {
         if (active) {
 #pragma unroll
@@ -440,11 +327,10 @@ __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
 // Adjoint: same tile staging; the upstream gradient of every distinct slot is gathered
 // once into LDS; per element dL/dkappa (stored directly) and the vertex gradients
 // (accumulated per tile node in LDS, then one global update per node and axis).
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 __device__ __forceinline__ void p1_bwd_tile(const TileArgs &a, int64_t tile)
 {
     constexpr int NP = D + 1;
-    using R = quad::P1Rule<D>;
     extern __shared__ __align__(16) unsigned char smem[];
     Lds<D> L(smem, a.nmax, a.smax);
     const int nn = a.tnode_ptr[tile + 1] - a.tnode_ptr[tile];
@@ -489,87 +375,17 @@ __device__ __forceinline__ void p1_bwd_tile(const TileArgs &a, int64_t tile)
                 G[i][j] = L.sacc[base + __popcll(r & ((1ull << p) - 1ull))];
             }
         }
-        double s = 0.0, msum = 0.0;
-#pragma unroll
-        for (int i = 0; i < NP; ++i)
-#pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                double bb = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) bb += g.B[i][d] * g.B[j][d];
-                s += G[i][j] * bb;
-                msum += G[i][j] * quad::p1_mass<D>(i, j);
-            }
+        double S[D][D], M[D][D], s, msum;
+        p1_adj_scalars<D, FORM>(a.form, g, G, S, M, s, msum);
         if (a.gkappa) {
             const double dk = g.vol * s;
             if (a.accumulate) a.gkappa[eu] += dk;
             else a.gkappa[eu] = dk;
         }
+        double gb[NP];
 #pragma unroll
-        for (int k = 0; k < NP; ++k)
-#pragma unroll
-            for (int d = 0; d < D; ++d) xbar[k][d] = 0.0;
-        double lterm = 0.0;
-        if constexpr (LOAD != FEM_LOAD_NONE) {
-            double gb[NP];
-#pragma unroll
-            for (int i = 0; i < NP; ++i) gb[i] = L.gr[ki[i]];
-#pragma unroll
-            for (int q = 0; q < R::nq; ++q) {
-                double p = 0.0;
-#pragma unroll
-                for (int i = 0; i < NP; ++i) p += gb[i] * R::lam(q, i);
-                double f;
-                if constexpr (LOAD == FEM_LOAD_SINPROD) {
-                    double xq[D], sn[D], cs[D];
-                    qpoint<D>(g, q, xq);
-#pragma unroll
-                    for (int d = 0; d < D; ++d) fem_sincospi(xq[d], &sn[d], &cs[d]);
-                    f = 1.0;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) f *= sn[d];
-                    const double wp = g.vol * R::w(q) * p;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        double df = M_PI * cs[d];
-#pragma unroll
-                        for (int d2 = 0; d2 < D; ++d2)
-                            if (d2 != d) df *= sn[d2];
-#pragma unroll
-                        for (int k = 0; k < NP; ++k) xbar[k][d] += wp * R::lam(q, k) * df;
-                    }
-                } else {
-                    f = a.fconst;
-                }
-                lterm += R::w(q) * p * f;
-            }
-        }
-        double T[D][D];
-#pragma unroll
-        for (int d1 = 0; d1 < D; ++d1)
-#pragma unroll
-            for (int d2 = 0; d2 < D; ++d2) {
-                double acc = 0.0;
-#pragma unroll
-                for (int i = 0; i < NP; ++i)
-#pragma unroll
-                    for (int j = 0; j < NP; ++j)
-                        acc += g.B[i][d1] * (G[i][j] + G[j][i]) * g.B[j][d2];
-                T[d1][d2] = acc;
-            }
-        const double scal = kap * s + a.c * msum + lterm;
-#pragma unroll
-        for (int d1 = 0; d1 < D; ++d1)
-#pragma unroll
-            for (int m = 0; m < D; ++m) {
-                double jb = 0.0;
-#pragma unroll
-                for (int d2 = 0; d2 < D; ++d2)
-                    jb += ((d1 == d2 ? scal : 0.0) - kap * T[d1][d2]) * g.inv[m][d2];
-                jb *= g.vol;
-                xbar[m + 1][d1] += jb;
-                xbar[0][d1] -= jb;
-            }
+        for (int i = 0; i < NP; ++i) gb[i] = (LOAD != FEM_LOAD_NONE) ? L.gr[ki[i]] : 0.0;
+        p1_adj_coords<D, FORM, LOAD>(a.form, g, kap, G, S, M, gb, s, msum, xbar);
     }
     if (!a.gcoords) {  // uniform: no coordinate gradient wanted
         if (MODE == kOrdered) publish_done(a.flags, tile);
@@ -661,42 +477,42 @@ __device__ __forceinline__ void p1_bwd_tile(const TileArgs &a, int64_t tile)
 // One mesh: the work item is a tile (through the colour-ordered list unless atomic).  The
 // forward asks for 5 wavefronts per SIMD (at most 102 registers; it needs 86): more
 // resident tiles hide more of the staging latency.
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_p1_tile_fwd(TileArgs a)
 {
     __shared__ int s_ticket;
     const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
-    p1_fwd_tile<D, LOAD, MODE>(a, (MODE == kAtomic || MODE == kTwoPass) ? i : a.tile_list[i]);
+    p1_fwd_tile<D, LOAD, MODE, FORM>(a, (MODE == kAtomic || MODE == kTwoPass) ? i : a.tile_list[i]);
 }
 
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 __global__ __launch_bounds__(1024) void k_p1_tile_bwd(TileArgs a)
 {
     __shared__ int s_ticket;
     const int64_t i = launch_index<MODE>(a.counter, &s_ticket);
-    p1_bwd_tile<D, LOAD, MODE>(a, (MODE == kAtomic || MODE == kTwoPass) ? i : a.tile_list[i]);
+    p1_bwd_tile<D, LOAD, MODE, FORM>(a, (MODE == kAtomic || MODE == kTwoPass) ? i : a.tile_list[i]);
 }
 
 // A batch of meshes: the work item (mesh << 32) | tile comes from the launch's item list
 // and the mesh's arguments from a device table.
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_p1_tile_fwd_batch(const TileArgs *__restrict__ tab,
                                                             const int64_t *__restrict__ items,
                                                             int32_t *counter)
 {
     __shared__ int s_ticket;
     const int64_t w = items[launch_index<MODE>(counter, &s_ticket)];
-    p1_fwd_tile<D, LOAD, MODE>(tab[w >> 32], w & 0xffffffffll);
+    p1_fwd_tile<D, LOAD, MODE, FORM>(tab[w >> 32], w & 0xffffffffll);
 }
 
-template <int D, int LOAD, int MODE>
+template <int D, int LOAD, int MODE, int FORM>
 __global__ __launch_bounds__(1024) void k_p1_tile_bwd_batch(const TileArgs *__restrict__ tab,
                                                             const int64_t *__restrict__ items,
                                                             int32_t *counter)
 {
     __shared__ int s_ticket;
     const int64_t w = items[launch_index<MODE>(counter, &s_ticket)];
-    p1_bwd_tile<D, LOAD, MODE>(tab[w >> 32], w & 0xffffffffll);
+    p1_bwd_tile<D, LOAD, MODE, FORM>(tab[w >> 32], w & 0xffffffffll);
 }
 
 template <int D>
@@ -725,8 +541,7 @@ TileArgs base_args(const fem_pattern *p, const fem_mesh *m, const fem_form *f, c
     a.tslot_ptr = p->tslot_ptr;
     a.tslot = p->tslot;
     a.kappa = coef;
-    a.c = f->reaction;
-    a.fconst = f->load_const[0];
+    a.form = p1_form_of(f);
     a.nmax = p->tile_max_nodes;
     a.smax = p->tile_max_slots;
     a.pred_ptr = p->tpred_ptr;
@@ -760,62 +575,90 @@ void launch(K kernel, const fem_pattern *p, TileArgs a, int mode, size_t lds, hi
     }
 }
 
-template <int D, int LOAD>
+template <int D, int LOAD, int FORM>
 int fwd_d(const fem_pattern *p, TileArgs a, int mode, hipStream_t s)
 {
     size_t lds = lds_bytes<D>(a.nmax, a.smax);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
-    if (mode == kOrdered) launch(k_p1_tile_fwd<D, LOAD, kOrdered>, p, a, mode, lds, s);
-    else if (mode == kTwoPass) launch(k_p1_tile_fwd<D, LOAD, kTwoPass>, p, a, mode, lds, s);
-    else if (mode == kColoured) launch(k_p1_tile_fwd<D, LOAD, kColoured>, p, a, mode, lds, s);
-    else launch(k_p1_tile_fwd<D, LOAD, kAtomic>, p, a, mode, lds, s);
+    if (mode == kOrdered) launch(k_p1_tile_fwd<D, LOAD, kOrdered, FORM>, p, a, mode, lds, s);
+    else if (mode == kTwoPass) launch(k_p1_tile_fwd<D, LOAD, kTwoPass, FORM>, p, a, mode, lds, s);
+    else if (mode == kColoured) launch(k_p1_tile_fwd<D, LOAD, kColoured, FORM>, p, a, mode, lds, s);
+    else launch(k_p1_tile_fwd<D, LOAD, kAtomic, FORM>, p, a, mode, lds, s);
     return FEM_OK;
 }
 
-template <int D, int LOAD>
+template <int D, int LOAD, int FORM>
 int bwd_d(const fem_pattern *p, TileArgs a, int mode, hipStream_t s)
 {
     size_t lds = lds_bytes<D>(a.nmax, a.smax);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
-    if (mode == kOrdered) launch(k_p1_tile_bwd<D, LOAD, kOrdered>, p, a, mode, lds, s);
-    else if (mode == kTwoPass) launch(k_p1_tile_bwd<D, LOAD, kTwoPass>, p, a, mode, lds, s);
-    else if (mode == kColoured) launch(k_p1_tile_bwd<D, LOAD, kColoured>, p, a, mode, lds, s);
-    else launch(k_p1_tile_bwd<D, LOAD, kAtomic>, p, a, mode, lds, s);
+    if (mode == kOrdered) launch(k_p1_tile_bwd<D, LOAD, kOrdered, FORM>, p, a, mode, lds, s);
+    else if (mode == kTwoPass) launch(k_p1_tile_bwd<D, LOAD, kTwoPass, FORM>, p, a, mode, lds, s);
+    else if (mode == kColoured) launch(k_p1_tile_bwd<D, LOAD, kColoured, FORM>, p, a, mode, lds, s);
+    else launch(k_p1_tile_bwd<D, LOAD, kAtomic, FORM>, p, a, mode, lds, s);
     return FEM_OK;
 }
 
-template <int D>
+template <int D, int FORM>
 int fwd_load(const fem_pattern *p, const TileArgs &a, int load, int mode, hipStream_t s)
 {
     switch (load) {
-    case FEM_LOAD_NONE: return fwd_d<D, FEM_LOAD_NONE>(p, a, mode, s);
-    case FEM_LOAD_CONST: return fwd_d<D, FEM_LOAD_CONST>(p, a, mode, s);
-    default: return fwd_d<D, FEM_LOAD_SINPROD>(p, a, mode, s);
+    case FEM_LOAD_NONE: return fwd_d<D, FEM_LOAD_NONE, FORM>(p, a, mode, s);
+    case FEM_LOAD_CONST: return fwd_d<D, FEM_LOAD_CONST, FORM>(p, a, mode, s);
+    case FEM_LOAD_POLY2: return fwd_d<D, FEM_LOAD_POLY2, FORM>(p, a, mode, s);
+    default: return fwd_d<D, FEM_LOAD_SINPROD, FORM>(p, a, mode, s);
+    }
+}
+
+template <int D, int FORM>
+int bwd_load(const fem_pattern *p, const TileArgs &a, int load, int mode, hipStream_t s)
+{
+    switch (load) {
+    case FEM_LOAD_NONE: return bwd_d<D, FEM_LOAD_NONE, FORM>(p, a, mode, s);
+    case FEM_LOAD_CONST: return bwd_d<D, FEM_LOAD_CONST, FORM>(p, a, mode, s);
+    case FEM_LOAD_POLY2: return bwd_d<D, FEM_LOAD_POLY2, FORM>(p, a, mode, s);
+    default: return bwd_d<D, FEM_LOAD_SINPROD, FORM>(p, a, mode, s);
     }
 }
 
 template <int D>
-int bwd_load(const fem_pattern *p, const TileArgs &a, int load, int mode, hipStream_t s)
+int fwd_form(const fem_pattern *p, const TileArgs &a, int form, int load, int mode, hipStream_t s)
 {
-    switch (load) {
-    case FEM_LOAD_NONE: return bwd_d<D, FEM_LOAD_NONE>(p, a, mode, s);
-    case FEM_LOAD_CONST: return bwd_d<D, FEM_LOAD_CONST>(p, a, mode, s);
-    default: return bwd_d<D, FEM_LOAD_SINPROD>(p, a, mode, s);
-    }
+    return form == FEM_FORM_HELMHOLTZ_SIGMA ? fwd_load<D, FEM_FORM_HELMHOLTZ_SIGMA>(p, a, load, mode, s)
+                                            : fwd_load<D, FEM_FORM_HELMHOLTZ>(p, a, load, mode, s);
 }
 
-template <int D, int LOAD>
+template <int D>
+int bwd_form(const fem_pattern *p, const TileArgs &a, int form, int load, int mode, hipStream_t s)
+{
+    return form == FEM_FORM_HELMHOLTZ_SIGMA ? bwd_load<D, FEM_FORM_HELMHOLTZ_SIGMA>(p, a, load, mode, s)
+                                            : bwd_load<D, FEM_FORM_HELMHOLTZ>(p, a, load, mode, s);
+}
+
+template <int D, int LOAD, int FORM>
 void batch_launch(const BatchFamily &f, const TileArgs *t, bool adj, int mode, size_t lds,
                   hipStream_t s)
 {
     if (adj) {
-        if (mode == kOrdered) launch_batch(k_p1_tile_bwd_batch<D, LOAD, kOrdered>, f, t, mode, f.T, lds, s);
-        else if (mode == kColoured) launch_batch(k_p1_tile_bwd_batch<D, LOAD, kColoured>, f, t, mode, f.T, lds, s);
-        else launch_batch(k_p1_tile_bwd_batch<D, LOAD, kAtomic>, f, t, mode, f.T, lds, s);
+        if (mode == kOrdered) launch_batch(k_p1_tile_bwd_batch<D, LOAD, kOrdered, FORM>, f, t, mode, f.T, lds, s);
+        else if (mode == kColoured) launch_batch(k_p1_tile_bwd_batch<D, LOAD, kColoured, FORM>, f, t, mode, f.T, lds, s);
+        else launch_batch(k_p1_tile_bwd_batch<D, LOAD, kAtomic, FORM>, f, t, mode, f.T, lds, s);
     } else {
-        if (mode == kOrdered) launch_batch(k_p1_tile_fwd_batch<D, LOAD, kOrdered>, f, t, mode, f.T, lds, s);
-        else if (mode == kColoured) launch_batch(k_p1_tile_fwd_batch<D, LOAD, kColoured>, f, t, mode, f.T, lds, s);
-        else launch_batch(k_p1_tile_fwd_batch<D, LOAD, kAtomic>, f, t, mode, f.T, lds, s);
+        if (mode == kOrdered) launch_batch(k_p1_tile_fwd_batch<D, LOAD, kOrdered, FORM>, f, t, mode, f.T, lds, s);
+        else if (mode == kColoured) launch_batch(k_p1_tile_fwd_batch<D, LOAD, kColoured, FORM>, f, t, mode, f.T, lds, s);
+        else launch_batch(k_p1_tile_fwd_batch<D, LOAD, kAtomic, FORM>, f, t, mode, f.T, lds, s);
+    }
+}
+
+template <int D, int FORM>
+void batch_loads(const BatchFamily &f, const TileArgs *t, int load, bool adj, int mode, size_t lds,
+                 hipStream_t s)
+{
+    switch (load) {
+    case FEM_LOAD_NONE: batch_launch<D, FEM_LOAD_NONE, FORM>(f, t, adj, mode, lds, s); break;
+    case FEM_LOAD_CONST: batch_launch<D, FEM_LOAD_CONST, FORM>(f, t, adj, mode, lds, s); break;
+    case FEM_LOAD_POLY2: batch_launch<D, FEM_LOAD_POLY2, FORM>(f, t, adj, mode, lds, s); break;
+    default: batch_launch<D, FEM_LOAD_SINPROD, FORM>(f, t, adj, mode, lds, s); break;
     }
 }
 
@@ -826,7 +669,7 @@ int batch_d(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fem_form
     const int mode = scatter_mode(flags);
     const bool acc = (flags & FEM_ACCUMULATE) != 0;
     std::vector<TileArgs> tab(f.mesh.size());
-    int load = -1;
+    int load = -1, form = -1;
     for (size_t j = 0; j < f.mesh.size(); ++j) {
         const int k = f.mesh[j];
         TileArgs a = base_args<D>(b->pats[k], &meshes[k], &forms[k], coef[k]);
@@ -851,6 +694,9 @@ int batch_d(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fem_form
         if (load < 0) load = lk;
         else if (load != lk)
             return fail(FEM_ERR_UNSUPPORTED, "the P1 meshes of a batch must share the load kind");
+        if (form < 0) form = forms[k].kind;
+        else if (form != forms[k].kind)
+            return fail(FEM_ERR_UNSUPPORTED, "the P1 meshes of a batch must share the form kind");
         std::memcpy(&tab[j], &a, sizeof(TileArgs));
     }
     const void *dev = nullptr;
@@ -858,11 +704,8 @@ int batch_d(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fem_form
     const TileArgs *t = (const TileArgs *)dev;
     const size_t lds = lds_bytes<D>(f.nmax, f.smax);
     if (lds > 160 * 1024) return fail(FEM_ERR_UNSUPPORTED, "tile needs more LDS than a CU has");
-    switch (load) {
-    case FEM_LOAD_NONE: batch_launch<D, FEM_LOAD_NONE>(f, t, io.adjoint, mode, lds, s); break;
-    case FEM_LOAD_CONST: batch_launch<D, FEM_LOAD_CONST>(f, t, io.adjoint, mode, lds, s); break;
-    default: batch_launch<D, FEM_LOAD_SINPROD>(f, t, io.adjoint, mode, lds, s); break;
-    }
+    if (form == FEM_FORM_HELMHOLTZ_SIGMA) batch_loads<D, FEM_FORM_HELMHOLTZ_SIGMA>(f, t, load, io.adjoint, mode, lds, s);
+    else batch_loads<D, FEM_FORM_HELMHOLTZ>(f, t, load, io.adjoint, mode, lds, s);
     FEM_HIP_TRY(hipGetLastError());
     return FEM_OK;
 }
@@ -890,7 +733,8 @@ int p1_tile_forward(const fem_pattern *p, const fem_mesh *m, const fem_form *f, 
     a.rhs = rhs;
     a.use_first = (mode == kColoured || mode == kOrdered) && !(flags & FEM_ACCUMULATE);
     const int load = rhs ? f->load : FEM_LOAD_NONE;
-    int rc = (m->dim == 2) ? fwd_load<2>(p, a, load, mode, s) : fwd_load<3>(p, a, load, mode, s);
+    int rc = (m->dim == 2) ? fwd_form<2>(p, a, f->kind, load, mode, s)
+                           : fwd_form<3>(p, a, f->kind, load, mode, s);
     if (rc != FEM_OK) return rc;
     FEM_HIP_TRY(hipGetLastError());
     if (mode == kTwoPass) {
@@ -916,7 +760,8 @@ int p1_tile_backward(const fem_pattern *p, const fem_mesh *m, const fem_form *f,
     a.accumulate = (flags & FEM_ACCUMULATE) != 0;
     a.use_first = (mode == kColoured || mode == kOrdered) && !a.accumulate;
     const int load = grhs ? f->load : FEM_LOAD_NONE;
-    int rc = (m->dim == 2) ? bwd_load<2>(p, a, load, mode, s) : bwd_load<3>(p, a, load, mode, s);
+    int rc = (m->dim == 2) ? bwd_form<2>(p, a, f->kind, load, mode, s)
+                           : bwd_form<3>(p, a, f->kind, load, mode, s);
     if (rc != FEM_OK) return rc;
     FEM_HIP_TRY(hipGetLastError());
     if (mode == kTwoPass && gcoords) FEM_TRY(reduce_nodes(p, m->dim, false, gcoords, a.accumulate, s));

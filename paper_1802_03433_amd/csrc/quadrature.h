@@ -7,6 +7,8 @@
 //   triangle, degree 2, 3 points:    (2/3, 1/6, 1/6) and permutations, w = 1/3
 //   tetrahedron, degree 2, 4 points: (a, b, b, b) and permutations, w = 1/4,
 //                                    a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20
+//   triangle, degree 5, 7 points (Radon 1948): the centroid, w = 9/40, and the orbits
+//     (a, a, 1 - 2a) for a = (6 -+ sqrt 15)/21 with w = (155 -+ sqrt 15)/1200
 //   tetrahedron, degree 5, 14 points (the positive rule with orbits
 //     S31(a1), S31(a2), S22(b); Walkington 2000, Keast 1986 family):
 //     a1 = 0.0927352503108912, w1 = 0.0734930431163619 (x4)
@@ -52,6 +54,24 @@ __host__ __device__ constexpr double p1_mass(int i, int j)
     for (int q = 0; q < P1Rule<D>::nq; ++q) s += P1Rule<D>::w(q) * P1Rule<D>::lam(q, i) * P1Rule<D>::lam(q, j);
     return s;
 }
+
+// ---- 7-point degree-5 triangle rule -------------------------------------------------
+struct Tri7 {
+    static constexpr int nq = 7;
+    static constexpr double r15 = 3.8729833462074169;  // sqrt(15)
+    static constexpr double a1 = (6.0 - r15) / 21.0, w1 = (155.0 - r15) / 1200.0;
+    static constexpr double a2 = (6.0 + r15) / 21.0, w2 = (155.0 + r15) / 1200.0;
+    __host__ __device__ static constexpr double lam(int q, int k)
+    {
+        if (q == 0) return 1.0 / 3.0;
+        if (q < 4) return k == q - 1 ? 1.0 - 2.0 * a1 : a1;
+        return k == q - 4 ? 1.0 - 2.0 * a2 : a2;
+    }
+    __host__ __device__ static constexpr double w(int q)
+    {
+        return q == 0 ? 9.0 / 40.0 : (q < 4 ? w1 : w2);
+    }
+};
 
 // ---- 14-point degree-5 tetrahedron rule ---------------------------------------------
 struct Tet14 {
