@@ -144,6 +144,50 @@ def _bench_p2(torch, fem, meshgen, dev, steps):
     return out
 
 
+def _bench_paper_2d(torch, fem, meshgen, dev, steps, n=1024):
+    """The worked example of Sec. 4.2 (sigma = [[1, -x-y], [x+y, 1]], lambda = 1,
+    f = -2(x^2 + y^2) + 36) on the unit square, n x n x 2 P1 triangles, beside the
+    Helmholtz form (kappa I, sin load) on the same mesh."""
+    m = meshgen.square_tri(n, seed=0)
+    dm = fem.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev))
+    kap = torch.ones((1, m.n_elems), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pat = fem.Pattern(dm)
+    torch.cuda.synchronize()
+    E, N, nnz = m.n_elems, m.n_nodes, pat.nnz
+    # conn 12 + kappa 8 + slots 36 per element, coords 16 + rhs 8 per node, values once
+    alg = E * (12 + 8 + 36) + N * (16 + 8) + nnz * 8
+    out = {"workload": f"unit square {n}^2 x 2 P1 triangles (jitter 0.2 h)", "n_elems": E,
+           "n_nodes": N, "nnz": nnz, "pattern_build_ms": (time.perf_counter() - t0) * 1e3}
+    values = torch.empty(nnz, dtype=torch.float64, device=dev)
+    rhs = torch.empty(N, dtype=torch.float64, device=dev)
+    forms = {"paper_example": fem.Form.paper_example(),
+             "helmholtz_sinprod": fem.Form("helmholtz", "sinprod", reaction=1.0)}
+    for fname, form in forms.items():
+        for sc in ("atomic", "coloured", "two-pass"):
+            def step():
+                fem.assemble(pat, dm, form, kap, values, rhs, scatter=sc)
+            step()
+            ms = _time_calls(torch, step, steps)
+            out[f"{fname}_{sc.replace('-', '_')}"] = {
+                "ms": ms, "elements_per_s": E / (ms * 1e-3), "alg_GBps": alg / (ms * 1e-3) / 1e9}
+    G, g = (torch.from_numpy(a).to(dev) for a in meshgen.upstream_grads(nnz, N, seed=0))
+    gk = torch.empty_like(kap)
+    gx = torch.empty_like(dm.coords)
+    form = forms["paper_example"]
+
+    def bwd():
+        fem.assemble_backward(pat, dm, form, kap, G, g, grad_coef=gk, grad_coords=gx)
+
+    bwd()
+    ms = _time_calls(torch, bwd, steps)
+    out["paper_example_bwd_atomic"] = {
+        "ms": ms, "bwd_over_fwd": ms / out["paper_example_atomic"]["ms"]}
+    pat.close()
+    return out
+
+
 def _bench_batch(torch, fem, meshgen, dev, steps, nmin=6, nmax=32):
     """512 meshes, n ~ U{nmin..nmax}, 6 n^3 tets each, half P1 Helmholtz (kappa, sin load),
     half P2 elasticity (lambda, mu, body force): one block-diagonal system.  With small
@@ -270,8 +314,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--sections", default="p1,p2,batch",
-                    help="extra legs to run: comma list of p1 (P1 variants and adjoint), p2, batch")
+    ap.add_argument("--sections", default="p1,paper,p2,batch",
+                    help="extra legs to run: comma list of p1 (P1 variants and adjoint), paper "
+                         "(the Sec. 4.2 example in 2D), p2, batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB copy three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -406,6 +451,9 @@ def main():
 
             bwd_det()
             extra[f"bwd_{sc.replace('-', '_')}_ms"] = _time_calls(torch, bwd_det, args.steps)
+    if not args.no_extra and "paper" in sections:
+        extra["paper_example_2d"] = _bench_paper_2d(torch, fem, meshgen, dev, args.steps)
+        torch.cuda.empty_cache()
     if not args.no_extra and "p2" in sections:
         extra["p2_elasticity"] = _bench_p2(torch, fem, meshgen, dev, max(5, args.steps // 3))
         torch.cuda.empty_cache()
