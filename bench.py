@@ -144,6 +144,114 @@ def _bench_p2(torch, fem, meshgen, dev, steps):
     return out
 
 
+def _bench_host_inclusive(torch, fem, m, kappa_np, form, reps=5):
+    """A host-to-host assembly of the 64^3 P1 workload, timed piece by piece as the paper
+    reports its totals (Sec. 6: allocation, copies, kernel): mesh and coefficients from
+    pinned host memory to the device, the one-time pattern build, the output allocation,
+    the assembly, and values + RHS back to pinned host memory."""
+    dev = torch.device("cuda:0")
+    h = {"coords": torch.from_numpy(m.coords).pin_memory(),
+         "conn": torch.from_numpy(m.conn).pin_memory(),
+         "kappa": torch.from_numpy(kappa_np).pin_memory()}
+    d = {k: torch.empty_like(v, device=dev) for k, v in h.items()}
+    h2d_bytes = sum(v.numel() * v.element_size() for v in h.values())
+
+    def h2d():
+        for k in h:
+            d[k].copy_(h[k], non_blocking=True)
+
+    h2d()
+    h2d_ms = _time_calls(torch, h2d, reps)
+    dm = fem.Mesh(d["coords"], d["conn"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pat = fem.Pattern(dm)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    alloc = []
+    for _ in range(reps):
+        torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        values = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+        rhs = torch.empty(pat.n_rows, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        alloc.append((time.perf_counter() - t0) * 1e3)
+        del values, rhs
+    values = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    rhs = torch.empty(pat.n_rows, dtype=torch.float64, device=dev)
+
+    def asm():
+        fem.assemble(pat, dm, form, d["kappa"], values, rhs)
+
+    asm()
+    asm_ms = _time_calls(torch, asm, reps)
+    hv = torch.empty(pat.nnz, dtype=torch.float64, pin_memory=True)
+    hr = torch.empty(pat.n_rows, dtype=torch.float64, pin_memory=True)
+
+    def d2h():
+        hv.copy_(values, non_blocking=True)
+        hr.copy_(rhs, non_blocking=True)
+
+    d2h()
+    d2h_ms = _time_calls(torch, d2h, reps)
+    d2h_bytes = (pat.nnz + pat.n_rows) * 8
+    alloc_ms = sorted(alloc)[len(alloc) // 2]
+    total = h2d_ms + alloc_ms + asm_ms + d2h_ms
+    pat.close()
+    return {"h2d_ms": h2d_ms, "h2d_GBps": h2d_bytes / (h2d_ms * 1e-3) / 1e9,
+            "pattern_build_ms": build_ms, "output_alloc_ms": alloc_ms, "assemble_ms": asm_ms,
+            "d2h_ms": d2h_ms, "d2h_GBps": d2h_bytes / (d2h_ms * 1e-3) / 1e9,
+            "total_ms_without_pattern": total,
+            "elements_per_s_host_to_host": m.n_elems / (total * 1e-3),
+            "assemble_share_of_total": asm_ms / total}
+
+
+def _bench_paper_layout(torch, fem, meshgen, dev, steps, pat, dm, kappa, form):
+    """The paper's own design (Alg. 1 with Fig. 2's thread mapping; the N x MAX_NZ row
+    layout with a column search, or the dense N x N matrix) against the tile kernels on
+    the same work.  Kernel time only (accumulate mode: no zero-fill in either)."""
+    out = {}
+
+    def pair(pat, dm, kap, form, ell, label):
+        values = torch.zeros(pat.nnz, dtype=torch.float64, device=dev)
+        rhs = torch.zeros(pat.n_rows, dtype=torch.float64, device=dev)
+        n = dm.n_nodes
+        pv = torch.zeros((n, ell[1].shape[1]) if ell is not None else (n, n),
+                         dtype=torch.float64, device=dev)
+        pr = torch.zeros(n, dtype=torch.float64, device=dev)
+
+        def ours():
+            fem.assemble(pat, dm, form, kap, values, rhs, accumulate=True)
+
+        def paper():
+            fem.assemble_paper(pat, dm, form, kap, ell=ell, values=pv, rhs=pr, accumulate=True)
+
+        ours()
+        paper()
+        t_ours = _time_calls(torch, ours, steps)
+        t_paper = _time_calls(torch, paper, steps)
+        out[label] = {"tile_kernel_ms": t_ours, "paper_design_ms": t_paper,
+                      "speedup": t_paper / t_ours, "n_elems": dm.n_elems, "n_nodes": n,
+                      "output": "dense N x N" if ell is None else f"N x MAX_NZ (MAX_NZ = {ell[1].shape[1]})"}
+        del pv
+
+    pair(pat, dm, kappa, form, fem.paper_ell(pat), "cube64_p1_sinprod_sparse")
+    m2 = meshgen.square_tri(1024, seed=0)
+    d2 = fem.Mesh(torch.from_numpy(m2.coords).to(dev), torch.from_numpy(m2.conn).to(dev))
+    p2 = fem.Pattern(d2)
+    k2 = torch.ones((1, m2.n_elems), dtype=torch.float64, device=dev)
+    pair(p2, d2, k2, fem.Form.paper_example(), fem.paper_ell(p2), "square1024_paper_example_sparse")
+    p2.close()
+    m3 = meshgen.square_tri(150, seed=0)
+    d3 = fem.Mesh(torch.from_numpy(m3.coords).to(dev), torch.from_numpy(m3.conn).to(dev))
+    p3 = fem.Pattern(d3)
+    k3 = torch.ones((1, m3.n_elems), dtype=torch.float64, device=dev)
+    pair(p3, d3, k3, fem.Form.paper_example(), None, "square150_paper_example_dense")
+    p3.close()
+    return out
+
+
 def _bench_paper_2d(torch, fem, meshgen, dev, steps, n=1024):
     """The worked example of Sec. 4.2 (sigma = [[1, -x-y], [x+y, 1]], lambda = 1,
     f = -2(x^2 + y^2) + 36) on the unit square, n x n x 2 P1 triangles, beside the
@@ -444,6 +552,7 @@ def main():
         extra["bwd_ms"] = bwd_ms
         extra["bwd_over_fwd"] = bwd_ms / ms_per_step
         extra["bwd_alg_GBps"] = _alg_bytes_bwd(E, N, nnz) / (bwd_ms * 1e-3) / 1e9
+        extra["host_inclusive"] = _bench_host_inclusive(torch, fem, m, kappa_np, form)
         for sc in ("coloured", "two-pass"):
             def bwd_det():
                 fem.assemble_backward(pat, dm, form, kappa, G, g, grad_coef=gk, grad_coords=gx,
@@ -453,6 +562,10 @@ def main():
             extra[f"bwd_{sc.replace('-', '_')}_ms"] = _time_calls(torch, bwd_det, args.steps)
     if not args.no_extra and "paper" in sections:
         extra["paper_example_2d"] = _bench_paper_2d(torch, fem, meshgen, dev, args.steps)
+        torch.cuda.empty_cache()
+        extra["paper_design_baseline"] = _bench_paper_layout(torch, fem, meshgen, dev,
+                                                             max(5, args.steps // 5), pat, dm,
+                                                             kappa, form)
         torch.cuda.empty_cache()
     if not args.no_extra and "p2" in sections:
         extra["p2_elasticity"] = _bench_p2(torch, fem, meshgen, dev, max(5, args.steps // 3))

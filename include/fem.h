@@ -300,6 +300,36 @@ int fem_assemble_backward_batch(fem_batch *batch, const fem_mesh *meshes, const 
 /* Releases a batch and its patterns (NULL is ignored).  Synchronises the device first. */
 void fem_batch_destroy(fem_batch *batch);
 
+/* ---------------------------------------------------------------------------------
+ * The paper's own assembly design, kept as a baseline for comparisons (Sec. 5).
+ *
+ * fem_paper_ell -- the row layout of the sparse variant of Sec. 5: nbr_len [n_nodes]
+ *   (gNbrNodeLen: stored entries of each row) and nbr_idx [n_nodes][max_nz]
+ *   (gNbrNodeIdx: the row's columns ascending, padded with -1), both caller-owned device
+ *   arrays written on the stream.  max_nz (MAX_NZ) must be at least the pattern's longest
+ *   row (fem_pattern_info.max_row; 7 for the 2D triangle meshes of the example).
+ *   Scalar P1 patterns only (UNSUPPORTED otherwise); INVALID_ARG for a small max_nz or
+ *   NULL arrays.
+ *
+ * fem_assemble_paper -- Alg. 1 with the thread mapping of Fig. 2: a 3D workgroup of
+ *   (integration point, local entry, element) threads, the elements' coordinates and
+ *   node indices staged in LDS, LDS atomic adds into the local matrices and vectors, then
+ *   one device-scope atomic add per local entry into the output.  Same forms, loads and
+ *   coef as fem_assemble (scalar P1 forms).
+ *   values: with nbr_idx, the sparse layout [n_nodes][max_nz] (entry k of row r is
+ *     column nbr_idx[r][k], found by a linear search along the row); with nbr_idx NULL,
+ *     the dense matrix [n_nodes][n_nodes] (row-major).
+ *   rhs: [n_nodes], may be NULL when form->load == FEM_LOAD_NONE.
+ *   flags: FEM_ACCUMULATE only (otherwise values and rhs are zero-filled first).
+ *   Asynchronous on the stream; errors as fem_assemble.
+ */
+int fem_paper_ell(const fem_pattern *pattern, int32_t max_nz, int32_t *nbr_len,
+                  int32_t *nbr_idx, void *stream);
+int fem_assemble_paper(const fem_pattern *pattern, const fem_mesh *mesh, const fem_form *form,
+                       const double *coef, const int32_t *nbr_len, const int32_t *nbr_idx,
+                       int32_t max_nz, double *values, double *rhs, unsigned flags,
+                       void *stream);
+
 /* Registers the allocator for the library's own device memory: the arrays a pattern or
  * batch handle holds (rowptr, colind, element-to-slot map, tile plan, colour lists, and
  * the partial sums of FEM_SCATTER_TWO_PASS, drawn at a pattern's first such call).  Not

@@ -14,7 +14,9 @@ from .api import (  # noqa: F401
     assemble_backward,
     assemble_backward_batch,
     assemble_batch,
+    assemble_paper,
     fem_assemble,
+    paper_ell,
     set_allocator,
     use_torch_allocator,
 )

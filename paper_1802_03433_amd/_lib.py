@@ -71,6 +71,8 @@ EXPORTS = (
     "fem_assemble_batch",
     "fem_assemble_backward_batch",
     "fem_batch_destroy",
+    "fem_paper_ell",
+    "fem_assemble_paper",
     "fem_set_allocator",
     "fem_error_string",
     "fem_last_error_message",
@@ -162,6 +164,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fem_assemble_backward_batch.argtypes = [P, pm, pf, P, P, P, P, P, ctypes.c_uint, P]
     L.fem_batch_destroy.argtypes = [P]
     L.fem_batch_destroy.restype = None
+    L.fem_paper_ell.argtypes = [P, ctypes.c_int32, P, P, P]
+    L.fem_assemble_paper.argtypes = [P, pm, pf, P, P, P, ctypes.c_int32, P, P, ctypes.c_uint, P]
     L.fem_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, P]
     L.fem_error_string.argtypes = [ctypes.c_int]
     L.fem_error_string.restype = ctypes.c_char_p
@@ -170,7 +174,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for n in ("fem_build_pattern", "fem_pattern_query", "fem_pattern_export",
               "fem_pattern_colours", "fem_assemble", "fem_assemble_backward",
               "fem_build_batch", "fem_batch_query", "fem_batch_offsets", "fem_batch_export",
-              "fem_assemble_batch", "fem_assemble_backward_batch", "fem_set_allocator"):
+              "fem_assemble_batch", "fem_assemble_backward_batch", "fem_set_allocator",
+              "fem_paper_ell", "fem_assemble_paper"):
         getattr(L, n).restype = ctypes.c_int
     return L
 

@@ -427,6 +427,54 @@ def assemble_backward_batch(batch: Batch, meshes: list, forms: list, coefs: list
     return (grad_coef if want_coef else None), (grad_coords if want_coords else None)
 
 
+def paper_ell(pattern: Pattern, max_nz: int | None = None):
+    """fem_paper_ell: the paper's sparse row layout, (nbr_len [N] int32,
+    nbr_idx [N, max_nz] int32, columns ascending, padded with -1)."""
+    max_nz = pattern.max_row if max_nz is None else int(max_nz)
+    dev = pattern.mesh.coords.device
+    n = pattern.mesh.n_nodes
+    ln = torch.empty(n, dtype=torch.int32, device=dev)
+    idx = torch.empty((n, max_nz), dtype=torch.int32, device=dev)
+    L.check(L.lib.fem_paper_ell(pattern.handle, max_nz, _ptr(ln), _ptr(idx), _stream_ptr(dev)),
+            "fem_paper_ell")
+    return ln, idx
+
+
+def assemble_paper(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tensor, ell=None,
+                   values: torch.Tensor | None = None, rhs: torch.Tensor | None = None,
+                   accumulate: bool = False):
+    """fem_assemble_paper (Alg. 1, Fig. 2): ell = (nbr_len, nbr_idx) from paper_ell gives
+    values [N, max_nz] in that layout; ell None gives the dense values [N, N]."""
+    _need(coef, torch.float64, "coef")
+    dev = mesh.coords.device
+    n = mesh.n_nodes
+    if ell is not None:
+        ln, idx = ell
+        _need(ln, torch.int32, "nbr_len")
+        _need(idx, torch.int32, "nbr_idx")
+        max_nz = int(idx.shape[1])
+        shape = (n, max_nz)
+    else:
+        ln = idx = None
+        max_nz = 0
+        shape = (n, n)
+    if values is None:
+        values = torch.empty(shape, dtype=torch.float64, device=dev)
+    if rhs is None and form.load != "none":
+        rhs = torch.empty(n, dtype=torch.float64, device=dev)
+    _need(values, torch.float64, "values")
+    if values.numel() != shape[0] * shape[1]:
+        raise ValueError(f"values must hold {shape[0]} x {shape[1]} entries")
+    if rhs is not None:
+        _need(rhs, torch.float64, "rhs")
+    ms, fs = mesh.cstruct(), form.cstruct()
+    rc = L.lib.fem_assemble_paper(pattern.handle, ctypes.byref(ms), ctypes.byref(fs), _ptr(coef),
+                                  _ptr(ln), _ptr(idx), max_nz, _ptr(values), _ptr(rhs),
+                                  L.ACCUMULATE if accumulate else 0, _stream_ptr(dev))
+    L.check(rc, "fem_assemble_paper")
+    return values, rhs
+
+
 class FemAssemble(torch.autograd.Function):
     """(coords, coef) -> (values, rhs) with the hand-written adjoint kernels as backward.
     The pattern, connectivity and form are non-tensor context; only the inputs are

@@ -1,0 +1,260 @@
+// The assembly design of the paper itself, run on this GPU as a baseline for the
+// tile-combined kernels (Sec. 5, Alg. 1, Fig. 2 and Fig. 3):
+//   - a workgroup holds Z elements and is a 3D block: thread (q, t, z) evaluates the
+//     integrand of local entry t of element z at quadrature point q (x: integration
+//     points, y: local entries, z: elements),
+//   - the elements' vertex coordinates and global node indices are first copied to LDS
+//     (Fig. 3's shared arrays),
+//   - every thread adds its weighted integrand value into the element's LDS entry with an
+//     LDS atomic add; after a barrier, one thread per entry adds the entry into the
+//     global output with a device-scope atomic add (Alg. 1),
+//   - outputs: the dense N x N matrix, or the sparse N x MAX_NZ row layout with the
+//     neighbour lists gNbrNodeLen / gNbrNodeIdx, where the column is found by a linear
+//     search along the row (the sparse variant of Sec. 5).
+// Local entries t < NP*NP are matrix entries (i = t / NP, j = t % NP), the next NP the
+// load vector.  The integrands are the P1 forms of p1_element.h evaluated point by point
+// with the load's rule, so every sum is exact where the tile kernels' is.
+#include "fem_internal.h"
+#include "p1_element.h"
+
+namespace fem {
+
+namespace {
+
+struct PaperArgs {
+    const double *coords;
+    int64_t N, E;
+    const int32_t *conn;
+    const double *kappa;
+    P1Form form;
+    const int32_t *nbr_len, *nbr_idx;  // sparse layout; nbr_idx NULL: dense N x N
+    int32_t max_nz;
+    double *values, *rhs;
+};
+
+// elements per workgroup: about 640 threads
+template <int D, int LOAD>
+struct PaperShape {
+    using R = typename LoadRule<D, LOAD>::type;
+    static constexpr int NP = D + 1;
+    static constexpr int NT = NP * NP + NP;
+    static constexpr int NQ = R::nq;
+    static constexpr int Z = (640 / (NQ * NT)) > 0 ? 640 / (NQ * NT) : 1;
+    static constexpr int THREADS = NQ * NT * Z;
+};
+
+template <int D, int FORM, int LOAD>
+__global__ __launch_bounds__(1024) void k_paper_assemble(PaperArgs a)
+{
+    using Sh = PaperShape<D, LOAD>;
+    using R = typename Sh::R;
+    constexpr int NP = Sh::NP, NT = Sh::NT, Z = Sh::Z;
+    __shared__ double xs[Z][NP][D];
+    __shared__ int32_t gidx[Z][NP];
+    __shared__ double loc[Z][NT];
+    const int q = threadIdx.x, t = threadIdx.y, z = threadIdx.z;
+    const int lin = (z * NT + t) * Sh::NQ + q;
+    const int64_t e0 = (int64_t)blockIdx.x * Z;
+    // Alg. 1, copy to shared memory
+    for (int u = lin; u < Z * NP; u += Sh::THREADS) {
+        const int zz = u / NP, k = u % NP;
+        const int64_t e = e0 + zz;
+        int32_t n = 0;
+        if (e < a.E) n = a.conn[k * a.E + e];
+        gidx[zz][k] = n;
+#pragma unroll
+        for (int d = 0; d < D; ++d) xs[zz][k][d] = (e < a.E) ? a.coords[d * a.N + n] : 0.0;
+    }
+    for (int u = lin; u < Z * NT; u += Sh::THREADS) loc[u / NT][u % NT] = 0.0;
+    __syncthreads();
+    const int64_t e = e0 + z;
+    const bool active = e < a.E;
+    if (active && (LOAD != FEM_LOAD_NONE || t < NP * NP)) {
+        // the integrand at point q, from the element's coordinates
+        Elem<D> g;
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int d = 0; d < D; ++d) g.x[k][d] = xs[z][k][d];
+        elem_geometry<D>(g);
+        double xq[D];
+        qpoint<D, R>(g, q, xq);
+        double v;
+        if (t < NP * NP) {
+            const int i = t / NP, j = t % NP;
+            // rows i and j of B by selects (a runtime index into g would go to scratch)
+            double Bi[D], Bj[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) Bi[d] = Bj[d] = g.B[0][d];
+#pragma unroll
+            for (int k = 1; k < NP; ++k)
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    if (i == k) Bi[d] = g.B[k][d];
+                    if (j == k) Bj[d] = g.B[k][d];
+                }
+            double s = 0.0;
+            if constexpr (FORM == FEM_FORM_HELMHOLTZ_SIGMA) {
+#pragma unroll
+                for (int r = 0; r < D; ++r)
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        double sg = a.form.sig[0][r][c];
+#pragma unroll
+                        for (int b = 0; b < D; ++b) sg += a.form.sig[1 + b][r][c] * xq[b];
+                        s += Bi[r] * sg * Bj[c];
+                    }
+            } else {
+#pragma unroll
+                for (int d = 0; d < D; ++d) s += Bi[d] * Bj[d];
+            }
+            v = R::w(q) * g.vol * (a.kappa[e] * s + a.form.c * R::lam(q, i) * R::lam(q, j));
+        } else {
+            const int i = t - NP * NP;
+            double fv;
+            if constexpr (LOAD == FEM_LOAD_SINPROD) {
+                fv = 1.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) fv *= fem_sinpi(xq[d]);
+            } else if constexpr (LOAD == FEM_LOAD_POLY2) {
+                fv = poly2<D>(a.form.poly, xq);
+            } else {
+                fv = a.form.fconst;
+            }
+            v = R::w(q) * g.vol * fv * R::lam(q, i);
+        }
+        atomicAdd(&loc[z][t], v);
+    }
+    __syncthreads();
+    if (!active || q != 0) return;
+    if (t < NP * NP) {
+        const int64_t row = gidx[z][t / NP];
+        const int32_t col = gidx[z][t % NP];
+        if (!a.nbr_idx) {
+            unsafeAtomicAdd(a.values + row * a.N + col, loc[z][t]);
+        } else {
+            // search the row's neighbour list for the column
+            const int32_t *nb = a.nbr_idx + row * a.max_nz;
+            const int len = a.nbr_len[row];
+            for (int k = 0; k < len; ++k)
+                if (nb[k] == col) {
+                    unsafeAtomicAdd(a.values + row * a.max_nz + k, loc[z][t]);
+                    break;
+                }
+        }
+    } else if (LOAD != FEM_LOAD_NONE) {
+        unsafeAtomicAdd(a.rhs + gidx[z][t - NP * NP], loc[z][t]);
+    }
+}
+
+template <int D, int FORM, int LOAD>
+void launch_paper(const PaperArgs &a, hipStream_t s)
+{
+    using Sh = PaperShape<D, LOAD>;
+    const unsigned blocks = (unsigned)((a.E + Sh::Z - 1) / Sh::Z);
+    hipLaunchKernelGGL((k_paper_assemble<D, FORM, LOAD>), dim3(blocks), dim3(Sh::NQ, Sh::NT, Sh::Z),
+                       0, s, a);
+}
+
+template <int D, int FORM>
+void paper_load(const PaperArgs &a, int load, hipStream_t s)
+{
+    switch (load) {
+    case FEM_LOAD_NONE: launch_paper<D, FORM, FEM_LOAD_NONE>(a, s); break;
+    case FEM_LOAD_CONST: launch_paper<D, FORM, FEM_LOAD_CONST>(a, s); break;
+    case FEM_LOAD_POLY2: launch_paper<D, FORM, FEM_LOAD_POLY2>(a, s); break;
+    default: launch_paper<D, FORM, FEM_LOAD_SINPROD>(a, s); break;
+    }
+}
+
+template <int D>
+void paper_form(const PaperArgs &a, int form, int load, hipStream_t s)
+{
+    if (form == FEM_FORM_HELMHOLTZ_SIGMA) paper_load<D, FEM_FORM_HELMHOLTZ_SIGMA>(a, load, s);
+    else paper_load<D, FEM_FORM_HELMHOLTZ>(a, load, s);
+}
+
+__global__ void k_ell_fill(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+                           int64_t N, int32_t max_nz, int32_t *__restrict__ len,
+                           int32_t *__restrict__ idx)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    const int32_t b = rowptr[r], n = rowptr[r + 1] - b;
+    len[r] = n;
+    for (int k = 0; k < max_nz; ++k) idx[r * max_nz + k] = k < n ? colind[b + k] : -1;
+}
+
+int check_scalar_p1(const fem_pattern *p)
+{
+    if (!p) return fail(FEM_ERR_INVALID_ARG, "pattern is NULL");
+    if (p->order != 1 || p->ncomp != 1)
+        return fail(FEM_ERR_UNSUPPORTED, "the paper's layout is provided for scalar P1 patterns");
+    return FEM_OK;
+}
+
+}  // namespace
+
+}  // namespace fem
+
+using namespace fem;
+
+extern "C" {
+
+int fem_paper_ell(const fem_pattern *p, int32_t max_nz, int32_t *nbr_len, int32_t *nbr_idx,
+                  void *stream)
+{
+    clear_error();
+    FEM_TRY(check_scalar_p1(p));
+    if (max_nz < p->max_row)
+        return fail(FEM_ERR_INVALID_ARG, "max_nz is below the pattern's longest row");
+    if (p->n_nodes == 0) return FEM_OK;
+    if (!nbr_len || !nbr_idx) return fail(FEM_ERR_INVALID_ARG, "nbr_len or nbr_idx is NULL");
+    hipLaunchKernelGGL(k_ell_fill, dim3(grid_for(p->n_nodes, 256)), dim3(256), 0,
+                       (hipStream_t)stream, p->rowptr_n, p->colind_n, p->n_nodes, max_nz, nbr_len,
+                       nbr_idx);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+int fem_assemble_paper(const fem_pattern *p, const fem_mesh *mesh, const fem_form *form,
+                       const double *coef, const int32_t *nbr_len, const int32_t *nbr_idx,
+                       int32_t max_nz, double *values, double *rhs, unsigned flags, void *stream)
+{
+    clear_error();
+    FEM_TRY(check_mesh(mesh, true));
+    FEM_TRY(check_same_mesh(p, mesh));
+    FEM_TRY(check_scalar_p1(p));
+    FEM_TRY(check_form(p, form));
+    if (flags & ~FEM_ACCUMULATE) return fail(FEM_ERR_INVALID_ARG, "fem_assemble_paper takes FEM_ACCUMULATE only");
+    if (nbr_idx && (!nbr_len || max_nz < p->max_row))
+        return fail(FEM_ERR_INVALID_ARG, "neighbour lists need nbr_len and max_nz >= the longest row");
+    if (mesh->n_elems > 0 && !coef) return fail(FEM_ERR_INVALID_ARG, "coef is NULL");
+    if (!values && p->n_nodes > 0) return fail(FEM_ERR_INVALID_ARG, "values is NULL");
+    if (form->load != FEM_LOAD_NONE && !rhs && p->n_nodes > 0)
+        return fail(FEM_ERR_INVALID_ARG, "rhs is NULL but the form has a load");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nv = nbr_idx ? p->n_nodes * (int64_t)max_nz : p->n_nodes * p->n_nodes;
+    double *r = form->load == FEM_LOAD_NONE ? nullptr : rhs;
+    if (!(flags & FEM_ACCUMULATE))
+        FEM_TRY(fill_zero2_f64(values, nv, r, r ? p->n_nodes : 0, s));
+    if (mesh->n_elems == 0) return FEM_OK;
+    PaperArgs a{};
+    a.coords = mesh->coords;
+    a.N = mesh->n_nodes;
+    a.E = mesh->n_elems;
+    a.conn = mesh->conn;
+    a.kappa = coef;
+    a.form = p1_form_of(form);
+    a.nbr_len = nbr_len;
+    a.nbr_idx = nbr_idx;
+    a.max_nz = max_nz;
+    a.values = values;
+    a.rhs = r;
+    if (mesh->dim == 2) paper_form<2>(a, form->kind, form->load, s);
+    else paper_form<3>(a, form->kind, form->load, s);
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
+}
+
+}  // extern "C"

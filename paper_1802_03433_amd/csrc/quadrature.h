@@ -83,11 +83,10 @@ struct Tet14 {
     {
         if (q < 4) return k == q ? 1.0 - 3.0 * a1 : a1;
         if (q < 8) return k == q - 4 ? 1.0 - 3.0 * a2 : a2;
-        // 6-point orbit: pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) carry b
-        constexpr int pi[6] = {0, 0, 0, 1, 1, 2};
-        constexpr int pj[6] = {1, 2, 3, 2, 3, 3};
-        int p = q - 8;
-        return (k == pi[p] || k == pj[p]) ? b : 0.5 - b;
+        // 6-point orbit: pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) carry b; nibble p of
+        // 0xCA6953 is the vertex mask of pair p (no array: runtime q, k stay in registers)
+        const int p = q - 8;
+        return ((0xCA6953 >> (4 * p + k)) & 1) ? b : 0.5 - b;
     }
     __host__ __device__ static constexpr double w(int q)
     {
