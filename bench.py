@@ -252,6 +252,60 @@ def _bench_paper_layout(torch, fem, meshgen, dev, steps, pat, dm, kappa, form):
     return out
 
 
+def _bench_rtc(torch, fem, meshgen, dev, steps, pat, dm, kappa, form):
+    """Runtime-compiled integrands (hipRTC): compile time, and a full assembly step (the
+    generated element kernel, then the tile scatter of its element matrices) against the
+    ahead-of-time template kernel on the same work."""
+    out = {}
+    t0 = time.perf_counter()
+    cf = fem.CompiledForm(3, load="sin(pi*x)*sin(pi*y)*sin(pi*z)", degree=2)
+    out["compile_s_cube"] = time.perf_counter() - t0
+    values = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    rhs = torch.empty(pat.n_rows, dtype=torch.float64, device=dev)
+
+    def rtc():
+        fem.assemble_rtc(pat, dm, cf, kappa, 1.0, values, rhs)
+
+    def aot():
+        fem.assemble(pat, dm, form, kappa, values, rhs)
+
+    rtc()
+    aot()
+    def elements_only():
+        cf.element_matrices(dm, kappa, 1.0)
+
+    elements_only()
+    out["cube64_p1_sinprod"] = {"rtc_ms": _time_calls(torch, rtc, steps),
+                                "template_ms": _time_calls(torch, aot, steps),
+                                "rtc_element_kernel_ms": _time_calls(torch, elements_only, steps)}
+    cf.close()
+    m2 = meshgen.square_tri(1024, seed=0)
+    d2 = fem.Mesh(torch.from_numpy(m2.coords).to(dev), torch.from_numpy(m2.conn).to(dev))
+    p2 = fem.Pattern(d2)
+    k2 = torch.ones((1, m2.n_elems), dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    cf2 = fem.CompiledForm(2, sigma=[["1", "-x-y"], ["x+y", "1"]], load="-2*(x*x+y*y)+36",
+                           degree=3)
+    out["compile_s_paper_example"] = time.perf_counter() - t0
+    v2 = torch.empty(p2.nnz, dtype=torch.float64, device=dev)
+    r2 = torch.empty(p2.n_rows, dtype=torch.float64, device=dev)
+    f2 = fem.Form.paper_example()
+
+    def rtc2():
+        fem.assemble_rtc(p2, d2, cf2, k2, 1.0, v2, r2)
+
+    def aot2():
+        fem.assemble(p2, d2, f2, k2, v2, r2)
+
+    rtc2()
+    aot2()
+    out["square1024_paper_example"] = {"rtc_ms": _time_calls(torch, rtc2, steps),
+                                       "template_ms": _time_calls(torch, aot2, steps)}
+    cf2.close()
+    p2.close()
+    return out
+
+
 def _bench_paper_2d(torch, fem, meshgen, dev, steps, n=1024):
     """The worked example of Sec. 4.2 (sigma = [[1, -x-y], [x+y, 1]], lambda = 1,
     f = -2(x^2 + y^2) + 36) on the unit square, n x n x 2 P1 triangles, beside the
@@ -566,6 +620,9 @@ def main():
         extra["paper_design_baseline"] = _bench_paper_layout(torch, fem, meshgen, dev,
                                                              max(5, args.steps // 5), pat, dm,
                                                              kappa, form)
+        torch.cuda.empty_cache()
+        extra["runtime_compiled"] = _bench_rtc(torch, fem, meshgen, dev, args.steps, pat, dm,
+                                               kappa, form)
         torch.cuda.empty_cache()
     if not args.no_extra and "p2" in sections:
         extra["p2_elasticity"] = _bench_p2(torch, fem, meshgen, dev, max(5, args.steps // 3))

@@ -67,6 +67,13 @@ extern "C" {
                                        column j the trial function.  The integrand is
                                        affine in x, so it is evaluated exactly at the
                                        element centroid */
+#define FEM_FORM_ELEMENT_MATRICES 4 /* element matrices computed by the caller (or by a
+                                       runtime-compiled integrand, fem_rtc_*): coef =
+                                       [NP*NP + NP][n_elems], entry (i, j) of element e
+                                       at coef[(i*NP + j)*n_elems + e], then the element
+                                       vectors (read under FEM_LOAD_ELEMENT); NP = dim+1.
+                                       P1 meshes; fem_assemble only (no adjoint, no
+                                       batches, no fem_assemble_paper) */
 
 /* ---- right-hand sides (v, f) ---- */
 #define FEM_LOAD_NONE 0    /* rhs untouched (may be NULL) */
@@ -74,6 +81,7 @@ extern "C" {
 #define FEM_LOAD_SINPROD 2 /* f = prod_a sin(pi x_a) (scalar forms), by quadrature */
 #define FEM_LOAD_POLY2 3   /* f = quadratic polynomial in x (fem_form.load_poly; scalar
                               forms), by a degree-5 rule: exact up to rounding */
+#define FEM_LOAD_ELEMENT 4 /* the element vectors given with FEM_FORM_ELEMENT_MATRICES */
 
 /* ---- flags ---- */
 #define FEM_SCATTER_ATOMIC 0x0u   /* scatter with device-scope FP64 atomic adds */
@@ -329,6 +337,42 @@ int fem_assemble_paper(const fem_pattern *pattern, const fem_mesh *mesh, const f
                        const double *coef, const int32_t *nbr_len, const int32_t *nbr_idx,
                        int32_t max_nz, double *values, double *rhs, unsigned flags,
                        void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Runtime-compiled integrands (Sec. 5: kernels generated from the weak form and compiled
+ * at run time).  The caller writes the matrix coefficient and the load of
+ *   (grad v, kappa_e sigma(x) grad u) + c (v, u) = (v, f)
+ * on P1 elements as C expressions in the point coordinates x, y, z (z = 0 in 2D), with
+ * the device math functions (sin, exp, pow, ...) and the constant pi; the library
+ * substitutes them into its kernel template and compiles it with hipRTC for the GPU.
+ *
+ * fem_rtc_compile -- sigma: dim*dim expressions, row-major (NULL: the identity); load:
+ *   one expression (NULL: no load); degree: the polynomial degree the quadrature must
+ *   integrate exactly (<= 2: the 3-point / 4-point rules, 3..5: the 7-point / 14-point
+ *   rules).  Runs on the host (no device needed).  *out: a library-owned handle.
+ *   INVALID_ARG with the compiler's log in fem_last_error_message() when an expression
+ *   does not compile.
+ * fem_rtc_source -- copies the generated source (NUL-terminated) into buf; returns FEM_OK,
+ *   or, when buf is NULL or smaller than needed, the size needed (a positive number).
+ * fem_rtc_element_matrices -- runs the compiled kernel: elmat [NP*NP + NP][n_elems] as
+ *   for FEM_FORM_ELEMENT_MATRICES (the vectors only when the form has a load); coef:
+ *   kappa [n_elems]; reaction: c.  Asynchronous on the stream.  The code object is
+ *   loaded on the current device at its first use there.
+ * fem_assemble_rtc -- element matrices into a stream-ordered scratch buffer, then
+ *   fem_assemble with FEM_FORM_ELEMENT_MATRICES and the given flags (every scatter mode).
+ *   rhs is written only when the form has a load.
+ * fem_rtc_destroy -- synchronises the devices it was loaded on and releases the handle.
+ */
+typedef struct fem_rtc fem_rtc; /* opaque, library-owned */
+int fem_rtc_compile(int32_t dim, const char *const *sigma, const char *load, int32_t degree,
+                    fem_rtc **out);
+int fem_rtc_source(const fem_rtc *rtc, char *buf, int64_t size);
+int fem_rtc_element_matrices(fem_rtc *rtc, const fem_mesh *mesh, const double *coef,
+                             double reaction, double *elmat, void *stream);
+int fem_assemble_rtc(const fem_pattern *pattern, const fem_mesh *mesh, fem_rtc *rtc,
+                     const double *coef, double reaction, double *values, double *rhs,
+                     unsigned flags, void *stream);
+void fem_rtc_destroy(fem_rtc *rtc);
 
 /* Registers the allocator for the library's own device memory: the arrays a pattern or
  * batch handle holds (rowptr, colind, element-to-slot map, tile plan, colour lists, and

@@ -6,6 +6,7 @@ not been built (python paper_1802_03433_amd/build.py).  There is no CPU fallback
 
 from .api import (  # noqa: F401
     Batch,
+    CompiledForm,
     FemAssemble,
     Form,
     Mesh,
@@ -15,6 +16,7 @@ from .api import (  # noqa: F401
     assemble_backward_batch,
     assemble_batch,
     assemble_paper,
+    assemble_rtc,
     fem_assemble,
     paper_ell,
     set_allocator,

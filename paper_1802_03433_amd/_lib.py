@@ -25,7 +25,8 @@ ERRORS = {
 FORM_HELMHOLTZ = 1
 FORM_ELASTICITY = 2
 FORM_HELMHOLTZ_SIGMA = 3
-LOAD = {"none": 0, "const": 1, "sinprod": 2, "poly2": 3}
+FORM_ELEMENT_MATRICES = 4
+LOAD = {"none": 0, "const": 1, "sinprod": 2, "poly2": 3, "element": 4}
 SCATTER_ATOMIC = 0x0
 SCATTER_COLOURED = 0x1
 ACCUMULATE = 0x2
@@ -73,6 +74,11 @@ EXPORTS = (
     "fem_batch_destroy",
     "fem_paper_ell",
     "fem_assemble_paper",
+    "fem_rtc_compile",
+    "fem_rtc_source",
+    "fem_rtc_element_matrices",
+    "fem_assemble_rtc",
+    "fem_rtc_destroy",
     "fem_set_allocator",
     "fem_error_string",
     "fem_last_error_message",
@@ -166,6 +172,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fem_batch_destroy.restype = None
     L.fem_paper_ell.argtypes = [P, ctypes.c_int32, P, P, P]
     L.fem_assemble_paper.argtypes = [P, pm, pf, P, P, P, ctypes.c_int32, P, P, ctypes.c_uint, P]
+    L.fem_rtc_compile.argtypes = [ctypes.c_int32, P, ctypes.c_char_p, ctypes.c_int32,
+                                  ctypes.POINTER(P)]
+    L.fem_rtc_source.argtypes = [P, ctypes.c_char_p, ctypes.c_int64]
+    L.fem_rtc_element_matrices.argtypes = [P, pm, P, ctypes.c_double, P, P]
+    L.fem_assemble_rtc.argtypes = [P, pm, P, P, ctypes.c_double, P, P, ctypes.c_uint, P]
+    L.fem_rtc_destroy.argtypes = [P]
+    L.fem_rtc_destroy.restype = None
     L.fem_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, P]
     L.fem_error_string.argtypes = [ctypes.c_int]
     L.fem_error_string.restype = ctypes.c_char_p
@@ -175,7 +188,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
               "fem_pattern_colours", "fem_assemble", "fem_assemble_backward",
               "fem_build_batch", "fem_batch_query", "fem_batch_offsets", "fem_batch_export",
               "fem_assemble_batch", "fem_assemble_backward_batch", "fem_set_allocator",
-              "fem_paper_ell", "fem_assemble_paper"):
+              "fem_paper_ell", "fem_assemble_paper", "fem_rtc_compile", "fem_rtc_source",
+              "fem_rtc_element_matrices", "fem_assemble_rtc"):
         getattr(L, n).restype = ctypes.c_int
     return L
 

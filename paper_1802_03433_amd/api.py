@@ -128,7 +128,8 @@ class Mesh:
 
 
 _FORMS = {"helmholtz": L.FORM_HELMHOLTZ, "elasticity": L.FORM_ELASTICITY,
-          "helmholtz-sigma": L.FORM_HELMHOLTZ_SIGMA}
+          "helmholtz-sigma": L.FORM_HELMHOLTZ_SIGMA,
+          "element-matrices": L.FORM_ELEMENT_MATRICES}
 
 
 @dataclass
@@ -473,6 +474,86 @@ def assemble_paper(pattern: Pattern, mesh: Mesh, form: Form, coef: torch.Tensor,
                                   L.ACCUMULATE if accumulate else 0, _stream_ptr(dev))
     L.check(rc, "fem_assemble_paper")
     return values, rhs
+
+
+class CompiledForm:
+    """A P1 integrand compiled at run time (fem_rtc_compile): sigma is dim x dim C
+    expressions in x, y, z (None: the identity), load one expression (None: no load),
+    degree the polynomial degree the quadrature must integrate exactly."""
+
+    def __init__(self, dim: int, sigma=None, load: str | None = None, degree: int = 2):
+        self.dim = int(dim)
+        self.has_load = load is not None
+        self._h = ctypes.c_void_p()
+        arr = None
+        if sigma is not None:
+            flat = [str(e) for row in sigma for e in row]
+            if len(flat) != self.dim * self.dim:
+                raise ValueError(f"sigma must be {dim} x {dim} expressions")
+            self._keep = [s.encode() for s in flat]
+            arr = (ctypes.c_char_p * len(flat))(*self._keep)
+        rc = L.lib.fem_rtc_compile(self.dim, arr, None if load is None else load.encode(),
+                                   int(degree), ctypes.byref(self._h))
+        L.check(rc, "fem_rtc_compile")
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise ValueError("compiled form has been closed")
+        return self._h
+
+    @property
+    def source(self) -> str:
+        n = L.lib.fem_rtc_source(self.handle, None, 0)
+        buf = ctypes.create_string_buffer(n)
+        L.check(L.lib.fem_rtc_source(self.handle, buf, n), "fem_rtc_source")
+        return buf.value.decode()
+
+    def element_matrices(self, mesh: Mesh, coef: torch.Tensor, reaction: float = 1.0):
+        """[NP*NP (+ NP)][E] element matrices (and vectors) of the compiled form."""
+        _need(coef, torch.float64, "coef")
+        np_ = self.dim + 1
+        out = torch.empty((np_ * np_ + (np_ if self.has_load else 0), mesh.n_elems),
+                          dtype=torch.float64, device=mesh.coords.device)
+        ms = mesh.cstruct()
+        L.check(L.lib.fem_rtc_element_matrices(self.handle, ctypes.byref(ms), _ptr(coef),
+                                               float(reaction), _ptr(out),
+                                               _stream_ptr(mesh.coords.device)),
+                "fem_rtc_element_matrices")
+        return out
+
+    def close(self):
+        if self._h:
+            L.lib.fem_rtc_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def assemble_rtc(pattern: Pattern, mesh: Mesh, form: CompiledForm, coef: torch.Tensor,
+                 reaction: float = 1.0, values: torch.Tensor | None = None,
+                 rhs: torch.Tensor | None = None, scatter: str = "atomic",
+                 accumulate: bool = False):
+    """fem_assemble_rtc; returns (values [nnz], rhs [n_rows] or None)."""
+    _need(coef, torch.float64, "coef")
+    dev = mesh.coords.device
+    if values is None:
+        values = torch.empty(pattern.nnz, dtype=torch.float64, device=dev)
+    if rhs is None and form.has_load:
+        rhs = torch.empty(pattern.n_rows, dtype=torch.float64, device=dev)
+    _need(values, torch.float64, "values")
+    if rhs is not None:
+        _need(rhs, torch.float64, "rhs")
+    ms = mesh.cstruct()
+    rc = L.lib.fem_assemble_rtc(pattern.handle, ctypes.byref(ms), form.handle, _ptr(coef),
+                                float(reaction), _ptr(values), _ptr(rhs),
+                                _flags(scatter, accumulate, False), _stream_ptr(dev))
+    L.check(rc, "fem_assemble_rtc")
+    return values, rhs if form.has_load else None
 
 
 class FemAssemble(torch.autograd.Function):

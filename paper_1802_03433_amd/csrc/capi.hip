@@ -44,8 +44,17 @@ int check_form(const fem_pattern *p, const fem_form *f)
 {
     if (!f) return fail(FEM_ERR_INVALID_ARG, "form is NULL");
     if (f->load != FEM_LOAD_NONE && f->load != FEM_LOAD_CONST && f->load != FEM_LOAD_SINPROD &&
-        f->load != FEM_LOAD_POLY2)
+        f->load != FEM_LOAD_POLY2 && f->load != FEM_LOAD_ELEMENT)
         return fail(FEM_ERR_INVALID_ARG, "unknown load kind");
+    if ((f->load == FEM_LOAD_ELEMENT) != (f->kind == FEM_FORM_ELEMENT_MATRICES) &&
+        !(f->kind == FEM_FORM_ELEMENT_MATRICES && f->load == FEM_LOAD_NONE))
+        return fail(FEM_ERR_INVALID_ARG,
+                    "FEM_LOAD_ELEMENT goes with FEM_FORM_ELEMENT_MATRICES, which takes it or none");
+    if (f->kind == FEM_FORM_ELEMENT_MATRICES) {
+        if (p->order != 1 || p->ncomp != 1)
+            return fail(FEM_ERR_UNSUPPORTED, "element matrices are provided for scalar P1 meshes");
+        return FEM_OK;
+    }
     if (f->kind == FEM_FORM_HELMHOLTZ || f->kind == FEM_FORM_HELMHOLTZ_SIGMA) {
         if (p->order != 1 || p->ncomp != 1)
             return fail(FEM_ERR_UNSUPPORTED, "Helmholtz forms are provided for scalar P1 meshes");
@@ -308,6 +317,8 @@ int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_
     const bool accumulate = (flags & FEM_ACCUMULATE) != 0;
     const bool elast = form->kind == FEM_FORM_ELASTICITY;
     if (flags & FEM_PREC_FP32) return fail(FEM_ERR_UNSUPPORTED, "the adjoint is FP64 only");
+    if (form->kind == FEM_FORM_ELEMENT_MATRICES)
+        return fail(FEM_ERR_UNSUPPORTED, "no adjoint for caller-given element matrices");
     if (elast && (flags & FEM_ELEMENT_SCATTER))
         return fail(FEM_ERR_UNSUPPORTED, "elasticity is assembled through the tile plan only");
     if (flags & FEM_VALIDATE) FEM_TRY(validate_elements(mesh, s));

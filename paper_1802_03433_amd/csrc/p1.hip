@@ -69,8 +69,9 @@ __global__ __launch_bounds__(kThreads) void k_p1_fwd(P1Args a)
 #pragma unroll
         for (int d = 0; d < D; ++d) g.x[k][d] = a.coords[d * a.N + v[k]];
     double A[NP][NP], b[NP];
-    p1_local<D, FORM, LOAD>(a.form, g, a.kappa[e], A, b);
-    if (a.err && g.det == 0.0) atomicOr(a.err, 1);
+    if constexpr (FORM == FEM_FORM_ELEMENT_MATRICES) p1_given<D, LOAD>(a.kappa, a.E, e, A, b);
+    else p1_local<D, FORM, LOAD>(a.form, g, a.kappa[e], A, b);
+    if (FORM != FEM_FORM_ELEMENT_MATRICES && a.err && g.det == 0.0) atomicOr(a.err, 1);
 #pragma unroll
     for (int i = 0; i < NP; ++i)
 #pragma unroll
@@ -223,6 +224,12 @@ template <int D>
 void dispatch_fwd(const fem_pattern *p, const P1Args &a, int form, int load, bool coloured,
                   hipStream_t s)
 {
+    if (form == FEM_FORM_ELEMENT_MATRICES) {
+        if (load == FEM_LOAD_ELEMENT)
+            run_fwd<D, FEM_LOAD_ELEMENT, FEM_FORM_ELEMENT_MATRICES>(p, a, coloured, s);
+        else run_fwd<D, FEM_LOAD_NONE, FEM_FORM_ELEMENT_MATRICES>(p, a, coloured, s);
+        return;
+    }
     if (form == FEM_FORM_HELMHOLTZ_SIGMA)
         dispatch_fwd_load<D, FEM_FORM_HELMHOLTZ_SIGMA>(p, a, load, coloured, s);
     else dispatch_fwd_load<D, FEM_FORM_HELMHOLTZ>(p, a, load, coloured, s);

@@ -254,6 +254,22 @@ __device__ __forceinline__ void p1_local(const P1Form &f, Elem<D> &g, double kap
     }
 }
 
+// Caller-given element matrix and vector (FEM_FORM_ELEMENT_MATRICES): entry (i, j) of
+// element e at m[(i*NP + j)*E + e], vector entry i at m[(NP*NP + i)*E + e]
+template <int D, int LOAD>
+__device__ __forceinline__ void p1_given(const double *m, int64_t E, int64_t e,
+                                         double A[D + 1][D + 1], double bv[D + 1])
+{
+    constexpr int NP = D + 1;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) A[i][j] = m[(int64_t)(i * NP + j) * E + e];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+        bv[i] = (LOAD != FEM_LOAD_NONE) ? m[(int64_t)(NP * NP + i) * E + e] : 0.0;
+}
+
 // Adjoint, first part: s = <S, M> (= <Gbar_e, B S B^T>), msum = <Gbar_e, M_ref>, and for
 // the sigma form S and M = B^T Gbar_e B.  g's geometry must be filled.
 template <int D, int FORM>

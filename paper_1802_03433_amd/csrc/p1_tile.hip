@@ -142,18 +142,22 @@ __device__ int stage_tile(const TileArgs &a, Lds<D> &L, int64_t tile, int nn, bo
 template <int D, int FORM, int LOAD>
 __device__ __forceinline__ void p1_element(const TileArgs &a, const double *xs, const uint64_t *rb,
                                            const int32_t *ust, uint64_t en, const uint32_t pr[D + 1],
-                                           double kap, double A[D + 1][D + 1], double bv[D + 1],
-                                           int ki[D + 1], int li[D + 1][D + 1])
+                                           double kap, int64_t eu, double A[D + 1][D + 1],
+                                           double bv[D + 1], int ki[D + 1], int li[D + 1][D + 1])
 {
     constexpr int NP = D + 1;
-    Elem<D> g;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        ki[k] = (int)((en >> (16 * k)) & 0xffffu);
+    for (int k = 0; k < NP; ++k) ki[k] = (int)((en >> (16 * k)) & 0xffffu);
+    if constexpr (FORM == FEM_FORM_ELEMENT_MATRICES) {
+        p1_given<D, LOAD>(a.kappa, a.E, eu, A, bv);
+    } else {
+        Elem<D> g;
 #pragma unroll
-        for (int d = 0; d < D; ++d) g.x[k][d] = xs[d * a.nmax + ki[k]];
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int d = 0; d < D; ++d) g.x[k][d] = xs[d * a.nmax + ki[k]];
+        p1_local<D, FORM, LOAD>(a.form, g, kap, A, bv);
     }
-    p1_local<D, FORM, LOAD>(a.form, g, kap, A, bv);
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
         const uint64_t r = rb[ki[i]];
@@ -202,19 +206,21 @@ __device__ __forceinline__ void p1_fwd_tile(const TileArgs &a, int64_t tile)
     uint64_t en = 0;
     uint32_t pr[NP];
     double kap = 0.0;
+    int64_t eu = e;
     int sc = 0;
     if (active) {
         en = a.enode[e];
 #pragma unroll
         for (int i = 0; i < NP; ++i) pr[i] = a.epos[i * a.E + e];
-        kap = a.kappa[a.telem ? a.telem[e] : e];
+        eu = a.telem ? a.telem[e] : e;
+        kap = a.kappa[eu];
         if (MODE != kAtomic) sc = a.esub[e];
     }
     const int ns = stage_tile<D>(a, L, tile, nn, a.use_first, false, MODE != kAtomic ? 1 : 0);
 
     double A[NP][NP], bv[NP];
     int ki[NP], li[NP][NP];
-    if (active) p1_element<D, FORM, LOAD>(a, L.xs, L.rb, L.ust, en, pr, kap, A, bv, ki, li);
+    if (active) p1_element<D, FORM, LOAD>(a, L.xs, L.rb, L.ust, en, pr, kap, eu, A, bv, ki, li);
     if (MODE == kAtomic) {
         if (active) {
 #pragma unroll
@@ -624,6 +630,10 @@ int bwd_load(const fem_pattern *p, const TileArgs &a, int load, int mode, hipStr
 template <int D>
 int fwd_form(const fem_pattern *p, const TileArgs &a, int form, int load, int mode, hipStream_t s)
 {
+    if (form == FEM_FORM_ELEMENT_MATRICES)
+        return load == FEM_LOAD_ELEMENT
+                   ? fwd_d<D, FEM_LOAD_ELEMENT, FEM_FORM_ELEMENT_MATRICES>(p, a, mode, s)
+                   : fwd_d<D, FEM_LOAD_NONE, FEM_FORM_ELEMENT_MATRICES>(p, a, mode, s);
     return form == FEM_FORM_HELMHOLTZ_SIGMA ? fwd_load<D, FEM_FORM_HELMHOLTZ_SIGMA>(p, a, load, mode, s)
                                             : fwd_load<D, FEM_FORM_HELMHOLTZ>(p, a, load, mode, s);
 }
@@ -694,6 +704,8 @@ int batch_d(fem_batch *b, BatchFamily &f, const fem_mesh *meshes, const fem_form
         if (load < 0) load = lk;
         else if (load != lk)
             return fail(FEM_ERR_UNSUPPORTED, "the P1 meshes of a batch must share the load kind");
+        if (forms[k].kind == FEM_FORM_ELEMENT_MATRICES)
+            return fail(FEM_ERR_UNSUPPORTED, "batches take no caller-given element matrices");
         if (form < 0) form = forms[k].kind;
         else if (form != forms[k].kind)
             return fail(FEM_ERR_UNSUPPORTED, "the P1 meshes of a batch must share the form kind");

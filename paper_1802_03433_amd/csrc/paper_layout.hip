@@ -226,6 +226,8 @@ int fem_assemble_paper(const fem_pattern *p, const fem_mesh *mesh, const fem_for
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_scalar_p1(p));
     FEM_TRY(check_form(p, form));
+    if (form->kind == FEM_FORM_ELEMENT_MATRICES)
+        return fail(FEM_ERR_UNSUPPORTED, "the paper's design evaluates integrands itself");
     if (flags & ~FEM_ACCUMULATE) return fail(FEM_ERR_INVALID_ARG, "fem_assemble_paper takes FEM_ACCUMULATE only");
     if (nbr_idx && (!nbr_len || max_nz < p->max_row))
         return fail(FEM_ERR_INVALID_ARG, "neighbour lists need nbr_len and max_nz >= the longest row");

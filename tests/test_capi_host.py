@@ -93,3 +93,24 @@ def test_set_allocator_python_arguments():
     with pytest.raises(ValueError):
         fem.set_allocator(release=lambda p: None)
     fem.set_allocator()  # back to the default
+
+
+def test_runtime_compiled_form_on_the_host():
+    """hipRTC compiles on the host: the generated source carries the expressions and the
+    rule's points; a bad expression is INVALID_ARG with the compiler's message."""
+    import paper_1802_03433_amd as fem
+
+    cf = fem.CompiledForm(2, sigma=[["1", "-x-y"], ["x+y", "1"]], load="-2*(x*x+y*y)+36",
+                          degree=3)
+    src = cf.source
+    assert "(double)(-x-y)" in src and "(double)(-2*(x*x+y*y)+36)" in src
+    assert "RL[7][3]" in src  # degree 3 in 2D: the 7-point rule
+    assert "RL[4][4]" in fem.CompiledForm(3, degree=2).source
+    cf.close()
+    with pytest.raises(fem.FemError) as e:
+        fem.CompiledForm(2, load="sin(pi*x) * no_such_name")
+    assert e.value.code == -1 and "no_such_name" in str(e.value)
+    with pytest.raises(fem.FemError):
+        fem.CompiledForm(4)
+    with pytest.raises(ValueError):
+        fem.CompiledForm(2, sigma=[["1"]])

@@ -1,0 +1,189 @@
+"""GPU tests of runtime-compiled integrands (Sec. 5: kernels generated from the weak form
+and compiled at run time, here with hipRTC) and of caller-given element matrices
+(FEM_FORM_ELEMENT_MATRICES, the scatter half they run through).  The Sec. 4.2 example and
+random affine sigma / quadratic loads written as expression strings match the oracle's
+exact integrals; the sin-product load written as a string matches the oracle's rule; a
+non-polynomial sigma matches a numpy evaluation of the same rule; element matrices from
+the oracle assemble to the oracle's matrix."""
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+from tests._util import scaled_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+PAPER_SIGMA = [np.eye(2), [[0.0, -1.0], [1.0, 0.0]], [[0.0, -1.0], [1.0, 0.0]]]
+PAPER_F = [36.0, 0, 0, 0, -2.0, 0, 0, -2.0, 0, 0]
+VARS = ["x", "y", "z"]
+
+
+def fem():
+    import paper_1802_03433_amd as F
+
+    return F
+
+
+def _dev(m):
+    F = fem()
+    dev = torch.device("cuda:0")
+    return F.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev), m.order)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _close(got, ref, scale, what=""):
+    ok, worst = scaled_close(got, ref, scale, RTOL)
+    assert ok, (what, worst)
+
+
+def _sigma_strings(sig, dim):
+    """Expressions of sigma(x) = S0 + sum_a x_a S_a."""
+    out = []
+    for r in range(dim):
+        row = []
+        for c in range(dim):
+            terms = [repr(float(sig[0][r][c]))]
+            terms += [f"({float(sig[1 + a][r][c])!r})*{VARS[a]}" for a in range(dim)]
+            row.append(" + ".join(terms))
+        out.append(row)
+    return out
+
+
+def _poly_string(p):
+    mono = ["1.0", "x", "y", "z", "x*x", "x*y", "x*z", "y*y", "y*z", "z*z"]
+    return " + ".join(f"({float(c)!r})*{mono[k]}" for k, c in enumerate(p))
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "coloured", "two-pass"])
+def test_paper_example_compiled_at_run_time(scatter):
+    F = fem()
+    m = meshgen.square_tri(24, seed=31)
+    d = _dev(m)
+    pat = F.Pattern(d)
+    cf = F.CompiledForm(2, sigma=[["1", "-x-y"], ["x+y", "1"]], load="-2*(x*x+y*y)+36",
+                        degree=3)
+    kap = torch.ones((1, m.n_elems), dtype=torch.float64, device="cuda")
+    v, r = F.assemble_rtc(pat, d, cf, kap, reaction=1.0, scatter=scatter)
+    rp, ci = oracle.pattern(3, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, np.ones(m.n_elems), 1.0, "poly2", None, rp, ci,
+                                            sigma=PAPER_SIGMA, poly=PAPER_F)
+    _close(_np(v), ov, oav, "values")
+    _close(_np(r), orhs, oar, "rhs")
+    # the same numbers as the ahead-of-time template form, within rounding
+    v2, r2 = F.assemble(pat, d, F.Form.paper_example(), kap, scatter=scatter)
+    _close(_np(v), _np(v2), oav, "vs template form")
+
+
+def test_random_affine_sigma_3d():
+    F = fem()
+    rng = np.random.default_rng(32)
+    sig = rng.normal(size=(4, 3, 3))
+    poly = rng.normal(size=10)
+    m = meshgen.cube_tet(7, seed=32)
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=32)
+    cf = F.CompiledForm(3, sigma=_sigma_strings(sig, 3), load=_poly_string(poly), degree=3)
+    v, r = F.assemble_rtc(pat, d, cf, torch.from_numpy(kappa).cuda(), reaction=0.6,
+                          scatter="coloured")
+    rp, ci = oracle.pattern(4, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 0.6, "poly2", None, rp, ci,
+                                            sigma=sig, poly=poly)
+    _close(_np(v), ov, oav, "values")
+    _close(_np(r), orhs, oar, "rhs")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sin_load_string_matches_rule(dim):
+    F = fem()
+    m = meshgen.square_tri(16, seed=33) if dim == 2 else meshgen.cube_tet(6, seed=33)
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=33)
+    load = "*".join(f"sin(pi*{VARS[a]})" for a in range(dim))
+    cf = F.CompiledForm(dim, load=load, degree=2)
+    v, r = F.assemble_rtc(pat, d, cf, torch.from_numpy(kappa).cuda(), reaction=1.0)
+    rp, ci = oracle.pattern(m.npe, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
+    _close(_np(v), ov, oav, "values")
+    _close(_np(r), orhs, oar, "rhs")
+    # no load: rhs untouched, matrix only
+    cf0 = F.CompiledForm(dim, degree=2)
+    v0, r0 = F.assemble_rtc(pat, d, cf0, torch.from_numpy(kappa).cuda(), reaction=1.0)
+    assert r0 is None
+    _close(_np(v0), ov, oav, "matrix only")
+
+
+def test_non_polynomial_sigma_element_matrices():
+    """sigma = (1 + x y / 2) I + sin(x) R has no closed form: the compiled kernel's element
+    matrices against numpy evaluating the same 3-point rule on every element."""
+    F = fem()
+    m = meshgen.square_tri(10, seed=34)
+    d = _dev(m)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=34)
+    cf = F.CompiledForm(2, sigma=[["1 + 0.5*x*y", "-sin(x)"], ["sin(x)", "1 + 0.5*x*y"]],
+                        load="exp(x - y)", degree=2)
+    em = _np(cf.element_matrices(d, torch.from_numpy(kappa).cuda(), reaction=0.3))
+    bary, w = oracle.quad_rule(2, 2)
+    X = m.coords[:, m.conn].transpose(2, 1, 0)  # [E][3][2]
+    J = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]], axis=2)  # J[e][a][m]
+    inv = np.linalg.inv(J)
+    B = np.concatenate([-inv.sum(1, keepdims=True), inv], axis=1)  # [E][3][2]
+    vol = 0.5 * np.abs(np.linalg.det(J))
+    ref = np.zeros((12, m.n_elems))
+    for q in range(len(w)):
+        P = np.einsum("k,ekd->ed", bary[q], X)
+        x, y = P[:, 0], P[:, 1]
+        S = np.empty((m.n_elems, 2, 2))
+        S[:, 0, 0] = S[:, 1, 1] = 1 + 0.5 * x * y
+        S[:, 0, 1] = -np.sin(x)
+        S[:, 1, 0] = np.sin(x)
+        g = np.einsum("eia,eab,ejb->eij", B, S, B)
+        A = w[q] * vol[:, None, None] * (kappa[0][:, None, None] * g
+                                        + 0.3 * np.outer(bary[q], bary[q])[None])
+        ref[:9] += A.reshape(m.n_elems, 9).T
+        ref[9:] += (w[q] * vol * np.exp(x - y))[None] * bary[q][:, None]
+    scale = np.abs(ref).max(axis=1, keepdims=True)
+    assert np.abs(em - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert (np.abs(em - ref) <= 1e-12 * scale + 1e-300).all()
+
+
+def test_element_matrices_form():
+    """Caller-given element matrices (here the oracle's own) assemble to the oracle's
+    matrix, through the tile plan and through the per-element path."""
+    F = fem()
+    m = meshgen.cube_tet(4, seed=35)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=35)[0]
+    em = np.zeros((20, m.n_elems))
+    for e in range(m.n_elems):
+        xv = m.coords[:, m.conn[:, e]].T
+        em[:16, e] = oracle.element_p1(xv, kappa[e], 0.8).ravel()
+        em[16:, e] = 0.7 * np.abs(np.linalg.det(xv[1:] - xv[0])) / 6.0 / 4.0
+    d = _dev(m)
+    pat = F.Pattern(d)
+    rp, ci = oracle.pattern(4, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa, 0.8, "const", [0.7], rp, ci)
+    form = F.Form("element-matrices", "element")
+    coef = torch.from_numpy(em).cuda()
+    for kw in ({"scatter": "atomic"}, {"scatter": "coloured"}, {"scatter": "two-pass"},
+               {"element_scatter": True}):
+        v, r = F.assemble(pat, d, form, coef, **kw)
+        _close(_np(v), ov, oav, ("values", kw))
+        _close(_np(r), orhs, oar, ("rhs", kw))
+    v, r = F.assemble(pat, d, F.Form("element-matrices", "none"), coef[:16].contiguous())
+    _close(_np(v), ov, oav, "matrix only")
+    G = torch.zeros(pat.nnz, dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FemError) as e:
+        F.assemble_backward(pat, d, form, coef, G, None)
+    assert e.value.code == -2
+    with pytest.raises(F.FemError) as e:
+        F.assemble_paper(pat, d, form, coef)
+    assert e.value.code == -2
