@@ -30,7 +30,8 @@ N_CELLS = 64
 # HBM traffic of the P1 forward kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # valid while the kernel's sources are the ones the counters were taken on
 HBM_PROFILE = os.path.join(ROOT, "profiles", "p1_tile_fwd_cube64_hbm.txt")
-KERNEL_SOURCES = ("paper_1802_03433_amd/csrc/p1_tile.hip", "paper_1802_03433_amd/csrc/fem_internal.h",
+KERNEL_SOURCES = ("paper_1802_03433_amd/csrc/p1_tile.hip", "paper_1802_03433_amd/csrc/p1_element.h",
+                  "paper_1802_03433_amd/csrc/fem_internal.h",
                   "paper_1802_03433_amd/csrc/quadrature.h", "paper_1802_03433_amd/csrc/tiles.hip",
                   "paper_1802_03433_amd/csrc/order.hip", "paper_1802_03433_amd/csrc/pattern.hip",
                   "paper_1802_03433_amd/build.py")
