@@ -361,6 +361,11 @@ int fem_assemble_paper(const fem_pattern *pattern, const fem_mesh *mesh, const f
  * fem_assemble_rtc -- element matrices into a stream-ordered scratch buffer, then
  *   fem_assemble with FEM_FORM_ELEMENT_MATRICES and the given flags (every scatter mode).
  *   rhs is written only when the form has a load.
+ * fem_assemble_backward_rtc -- adjoint with respect to the coefficient:
+ *   grad_coef[e] = dL/dkappa_e = <grad_values_e, K_e>, K_e the element matrix at kappa = 1,
+ *   c = 0 (the form is linear in kappa), for L as in fem_assemble_backward.  grad_coords
+ *   must be NULL (UNSUPPORTED otherwise: the expressions are not differentiated in x);
+ *   grad_rhs is not read (the load does not depend on kappa).  flags: FEM_ACCUMULATE.
  * fem_rtc_destroy -- synchronises the devices it was loaded on and releases the handle.
  */
 typedef struct fem_rtc fem_rtc; /* opaque, library-owned */
@@ -372,6 +377,10 @@ int fem_rtc_element_matrices(fem_rtc *rtc, const fem_mesh *mesh, const double *c
 int fem_assemble_rtc(const fem_pattern *pattern, const fem_mesh *mesh, fem_rtc *rtc,
                      const double *coef, double reaction, double *values, double *rhs,
                      unsigned flags, void *stream);
+int fem_assemble_backward_rtc(const fem_pattern *pattern, const fem_mesh *mesh, fem_rtc *rtc,
+                              const double *coef, double reaction, const double *grad_values,
+                              const double *grad_rhs, double *grad_coef, double *grad_coords,
+                              unsigned flags, void *stream);
 void fem_rtc_destroy(fem_rtc *rtc);
 
 /* Registers the allocator for the library's own device memory: the arrays a pattern or

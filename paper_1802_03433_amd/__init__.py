@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     assemble_backward_batch,
     assemble_batch,
     assemble_paper,
+    assemble_backward_rtc,
     assemble_rtc,
     fem_assemble,
     paper_ell,

@@ -78,6 +78,7 @@ EXPORTS = (
     "fem_rtc_source",
     "fem_rtc_element_matrices",
     "fem_assemble_rtc",
+    "fem_assemble_backward_rtc",
     "fem_rtc_destroy",
     "fem_set_allocator",
     "fem_error_string",
@@ -177,6 +178,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fem_rtc_source.argtypes = [P, ctypes.c_char_p, ctypes.c_int64]
     L.fem_rtc_element_matrices.argtypes = [P, pm, P, ctypes.c_double, P, P]
     L.fem_assemble_rtc.argtypes = [P, pm, P, P, ctypes.c_double, P, P, ctypes.c_uint, P]
+    L.fem_assemble_backward_rtc.argtypes = [P, pm, P, P, ctypes.c_double, P, P, P, P,
+                                            ctypes.c_uint, P]
     L.fem_rtc_destroy.argtypes = [P]
     L.fem_rtc_destroy.restype = None
     L.fem_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, P]
@@ -189,7 +192,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
               "fem_build_batch", "fem_batch_query", "fem_batch_offsets", "fem_batch_export",
               "fem_assemble_batch", "fem_assemble_backward_batch", "fem_set_allocator",
               "fem_paper_ell", "fem_assemble_paper", "fem_rtc_compile", "fem_rtc_source",
-              "fem_rtc_element_matrices", "fem_assemble_rtc"):
+              "fem_rtc_element_matrices", "fem_assemble_rtc", "fem_assemble_backward_rtc"):
         getattr(L, n).restype = ctypes.c_int
     return L
 

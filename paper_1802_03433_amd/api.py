@@ -556,6 +556,27 @@ def assemble_rtc(pattern: Pattern, mesh: Mesh, form: CompiledForm, coef: torch.T
     return values, rhs if form.has_load else None
 
 
+def assemble_backward_rtc(pattern: Pattern, mesh: Mesh, form: CompiledForm, coef: torch.Tensor,
+                          grad_values: torch.Tensor | None, reaction: float = 1.0,
+                          grad_coef: torch.Tensor | None = None, accumulate: bool = False):
+    """fem_assemble_backward_rtc: dL/dkappa [1, E] for L = <grad_values, values> (+ a
+    load term, which does not depend on kappa)."""
+    _need(coef, torch.float64, "coef")
+    if grad_coef is None:
+        grad_coef = torch.empty_like(coef)
+    if grad_values is not None:
+        _need(grad_values, torch.float64, "grad_values")
+    _need(grad_coef, torch.float64, "grad_coef")
+    dev = mesh.coords.device
+    ms = mesh.cstruct()
+    rc = L.lib.fem_assemble_backward_rtc(pattern.handle, ctypes.byref(ms), form.handle,
+                                         _ptr(coef), float(reaction), _ptr(grad_values), None,
+                                         _ptr(grad_coef), None,
+                                         L.ACCUMULATE if accumulate else 0, _stream_ptr(dev))
+    L.check(rc, "fem_assemble_backward_rtc")
+    return grad_coef
+
+
 class FemAssemble(torch.autograd.Function):
     """(coords, coef) -> (values, rhs) with the hand-written adjoint kernels as backward.
     The pattern, connectivity and form are non-tensor context; only the inputs are

@@ -204,6 +204,26 @@ std::string make_source(int D, const char *const *sigma, const char *load, int d
     return s;
 }
 
+// dL/dkappa_e = <Gbar_e, K_e> with K_e the element matrix at kappa = 1, c = 0 (the form
+// is linear in kappa): Gbar_e gathered through the element-to-slot map
+__global__ void k_rtc_dkappa(const int32_t *__restrict__ slot, int64_t E, int np,
+                             const double *__restrict__ K, const double *__restrict__ gvalues,
+                             double *__restrict__ gcoef, bool accumulate)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double s = 0.0;
+    for (int t = 0; t < np * np; ++t) s += gvalues[slot[t * E + e]] * K[t * E + e];
+    if (accumulate) gcoef[e] += s;
+    else gcoef[e] = s;
+}
+
+__global__ void k_fill_ones(double *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 1.0;
+}
+
 int rtc_function(fem_rtc *r, hipFunction_t *fn)
 {
     int dev = 0;
@@ -338,6 +358,47 @@ int fem_assemble_rtc(const fem_pattern *p, const fem_mesh *mesh, fem_rtc *r, con
                           flags, stream);
     if (elmat) (void)hipFreeAsync(elmat, s);
     return rc;
+}
+
+int fem_assemble_backward_rtc(const fem_pattern *p, const fem_mesh *mesh, fem_rtc *r,
+                              const double *coef, double reaction, const double *grad_values,
+                              const double *grad_rhs, double *grad_coef, double *grad_coords,
+                              unsigned flags, void *stream)
+{
+    clear_error();
+    (void)coef;
+    (void)reaction;
+    (void)grad_rhs;  // the load does not depend on kappa
+    if (!r) return fail(FEM_ERR_INVALID_ARG, "rtc is NULL");
+    FEM_TRY(check_mesh(mesh, true));
+    FEM_TRY(check_same_mesh(p, mesh));
+    if (mesh->order != 1 || mesh->dim != r->dim || p->ncomp != 1)
+        return fail(FEM_ERR_INVALID_ARG, "the mesh does not match the compiled form (scalar P1, its dim)");
+    if (grad_coords)
+        return fail(FEM_ERR_UNSUPPORTED, "compiled integrands are not differentiated in x");
+    if (flags & ~FEM_ACCUMULATE)
+        return fail(FEM_ERR_INVALID_ARG, "fem_assemble_backward_rtc takes FEM_ACCUMULATE only");
+    const int64_t E = mesh->n_elems;
+    if (!grad_coef || E == 0) return FEM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (!grad_values) {
+        if (!(flags & FEM_ACCUMULATE)) FEM_TRY(fill_zero_f64(grad_coef, E, s));
+        return FEM_OK;
+    }
+    const int np = r->np;
+    const int64_t rows = np * np + (r->has_load ? np : 0);
+    double *buf = nullptr;
+    FEM_HIP_TRY(hipMallocAsync((void **)&buf, sizeof(double) * (size_t)((rows + 1) * E), s));
+    double *ones = buf + rows * E;
+    hipLaunchKernelGGL(k_fill_ones, dim3(grid_for(E, 256)), dim3(256), 0, s, ones, E);
+    int rc = fem_rtc_element_matrices(r, mesh, ones, 0.0, buf, stream);
+    if (rc == FEM_OK)
+        hipLaunchKernelGGL(k_rtc_dkappa, dim3(grid_for(E, 256)), dim3(256), 0, s, p->slot, E, np,
+                           buf, grad_values, grad_coef, (flags & FEM_ACCUMULATE) != 0);
+    (void)hipFreeAsync(buf, s);
+    if (rc != FEM_OK) return rc;
+    FEM_HIP_TRY(hipGetLastError());
+    return FEM_OK;
 }
 
 void fem_rtc_destroy(fem_rtc *r)

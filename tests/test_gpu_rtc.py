@@ -187,3 +187,36 @@ def test_element_matrices_form():
     with pytest.raises(F.FemError) as e:
         F.assemble_paper(pat, d, form, coef)
     assert e.value.code == -2
+
+
+def test_compiled_form_coefficient_adjoint():
+    """dL/dkappa of a compiled form (the element matrices at kappa = 1 contracted with the
+    upstream value gradient) against the oracle's adjoint of the same form."""
+    import ctypes
+
+    from paper_1802_03433_amd import _lib
+
+    F = fem()
+    m = meshgen.square_tri(12, seed=36)
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=36)
+    kap = torch.from_numpy(kappa).cuda()
+    cf = F.CompiledForm(2, sigma=[["1", "-x-y"], ["x+y", "1"]], load="-2*(x*x+y*y)+36",
+                        degree=3)
+    G, g = meshgen.upstream_grads(pat.nnz, pat.n_rows, seed=36)
+    Gt = torch.from_numpy(G).cuda()
+    gk = F.assemble_backward_rtc(pat, d, cf, kap, Gt, reaction=1.0)
+    rp, ci = oracle.pattern(3, 1, m.n_nodes, m.conn)
+    dk, adk, _, _ = oracle.backward_p1(m, kappa[0], 1.0, "poly2", None, rp, ci, G, g,
+                                       want_coords=False, sigma=PAPER_SIGMA, poly=PAPER_F)
+    _close(_np(gk)[0], dk, adk, "dkappa")
+    F.assemble_backward_rtc(pat, d, cf, kap, Gt, reaction=1.0, grad_coef=gk, accumulate=True)
+    _close(_np(gk)[0], 2 * dk, 2 * adk, "accumulated")
+    ms = d.cstruct()
+    rc = _lib.lib.fem_assemble_backward_rtc(pat.handle, ctypes.byref(ms), cf.handle,
+                                            ctypes.c_void_p(kap.data_ptr()), 1.0,
+                                            ctypes.c_void_p(Gt.data_ptr()), None,
+                                            ctypes.c_void_p(gk.data_ptr()),
+                                            ctypes.c_void_p(d.coords.data_ptr()), 0, None)
+    assert rc == -2  # no coordinate gradient for compiled expressions
