@@ -345,6 +345,7 @@ int fem_assemble_paper(const fem_pattern *pattern, const fem_mesh *mesh, const f
  * on P1 elements as C expressions in the point coordinates x, y, z (z = 0 in 2D), with
  * the device math functions (sin, exp, pow, ...) and the constant pi; the library
  * substitutes them into its kernel template and compiles it with hipRTC for the GPU.
+ * The text is compiled as given, as device code: pass only trusted expressions.
  *
  * fem_rtc_compile -- sigma: dim*dim expressions, row-major (NULL: the identity); load:
  *   one expression (NULL: no load); degree: the polynomial degree the quadrature must
