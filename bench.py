@@ -608,6 +608,8 @@ def main():
         extra["bwd_over_fwd"] = bwd_ms / ms_per_step
         extra["bwd_alg_GBps"] = _alg_bytes_bwd(E, N, nnz) / (bwd_ms * 1e-3) / 1e9
         extra["host_inclusive"] = _bench_host_inclusive(torch, fem, m, kappa_np, form)
+        tuned = fem.autotune(dm, form, kappa, scatter=args.scatter, reps=10)
+        extra["autotune"] = {k: tuned[k] for k in ("label", "ms", "timings", "key")}
         for sc in ("coloured", "two-pass"):
             def bwd_det():
                 fem.assemble_backward(pat, dm, form, kappa, G, g, grad_coef=gk, grad_coords=gx,

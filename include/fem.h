@@ -384,6 +384,21 @@ int fem_assemble_backward_rtc(const fem_pattern *pattern, const fem_mesh *mesh, 
                               unsigned flags, void *stream);
 void fem_rtc_destroy(fem_rtc *rtc);
 
+/* fem_autotune -- chooses the tile plan of a mesh by measurement: candidate c builds a
+ *   pattern with build_flags[c] (the tile size bits, FEM_INPUT_ORDER) and times `reps`
+ *   calls of fem_assemble with assemble_flags | extra_flags[c] (extra_flags may be NULL;
+ *   FEM_ELEMENT_SCATTER there times the per-element path without tiles) on the stream
+ *   with HIP events.  ms[c] receives the average milliseconds per call, or -1 for a
+ *   candidate the plan does not take (it is skipped); *best the index of the fastest.
+ *   Synchronises the stream; allocates and frees its own patterns and outputs.  The
+ *   choice is the caller's to keep (the Python layer caches it as JSON, keyed by
+ *   architecture, form, element kind and size).  UNSUPPORTED when no candidate ran;
+ *   INVALID_ARG for bad arguments or FEM_ACCUMULATE. */
+int fem_autotune(const fem_mesh *mesh, int32_t ncomp, const fem_form *form, const double *coef,
+                 unsigned assemble_flags, int32_t n_candidates, const unsigned *build_flags,
+                 const unsigned *extra_flags, int32_t reps, double *ms, int32_t *best,
+                 void *stream);
+
 /* Registers the allocator for the library's own device memory: the arrays a pattern or
  * batch handle holds (rowptr, colind, element-to-slot map, tile plan, colour lists, and
  * the partial sums of FEM_SCATTER_TWO_PASS, drawn at a pattern's first such call).  Not

@@ -18,6 +18,7 @@ from .api import (  # noqa: F401
     assemble_paper,
     assemble_backward_rtc,
     assemble_rtc,
+    autotune,
     fem_assemble,
     paper_ell,
     set_allocator,

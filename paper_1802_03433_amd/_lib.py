@@ -80,6 +80,7 @@ EXPORTS = (
     "fem_assemble_rtc",
     "fem_assemble_backward_rtc",
     "fem_rtc_destroy",
+    "fem_autotune",
     "fem_set_allocator",
     "fem_error_string",
     "fem_last_error_message",
@@ -182,6 +183,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                             ctypes.c_uint, P]
     L.fem_rtc_destroy.argtypes = [P]
     L.fem_rtc_destroy.restype = None
+    L.fem_autotune.argtypes = [pm, ctypes.c_int32, pf, P, ctypes.c_uint, ctypes.c_int32, P, P,
+                               ctypes.c_int32, P, ctypes.POINTER(ctypes.c_int32), P]
     L.fem_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, P]
     L.fem_error_string.argtypes = [ctypes.c_int]
     L.fem_error_string.restype = ctypes.c_char_p
@@ -192,7 +195,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
               "fem_build_batch", "fem_batch_query", "fem_batch_offsets", "fem_batch_export",
               "fem_assemble_batch", "fem_assemble_backward_batch", "fem_set_allocator",
               "fem_paper_ell", "fem_assemble_paper", "fem_rtc_compile", "fem_rtc_source",
-              "fem_rtc_element_matrices", "fem_assemble_rtc", "fem_assemble_backward_rtc"):
+              "fem_rtc_element_matrices", "fem_assemble_rtc", "fem_assemble_backward_rtc",
+              "fem_autotune"):
         getattr(L, n).restype = ctypes.c_int
     return L
 

@@ -8,6 +8,9 @@ nothing here computes any part of the method.
 from __future__ import annotations
 
 import ctypes
+import json
+import math
+import os
 from dataclasses import dataclass, field
 
 import torch
@@ -575,6 +578,73 @@ def assemble_backward_rtc(pattern: Pattern, mesh: Mesh, form: CompiledForm, coef
                                          L.ACCUMULATE if accumulate else 0, _stream_ptr(dev))
     L.check(rc, "fem_assemble_backward_rtc")
     return grad_coef
+
+
+def _tune_key(mesh: Mesh, form: Form, scatter: str, fp32: bool) -> str:
+    """Cache key: architecture, form, load, element kind, scatter mode, precision and the
+    size bucket (nearest power of two of the element count)."""
+    arch = torch.cuda.get_device_properties(mesh.coords.device).gcnArchName.split(":")[0]
+    bucket = int(round(math.log2(max(mesh.n_elems, 1))))
+    return (f"{arch}|{form.kind}|{form.load}|P{mesh.order}|{mesh.dim}D|{scatter}|"
+            f"{'fp32' if fp32 else 'fp64'}|E~2^{bucket}")
+
+
+def _default_candidates(mesh: Mesh):
+    """(label, pattern kwargs, element_scatter) triples the tuner times."""
+    if mesh.order == 2:
+        return [(f"tile{t}", {"tile": t}, False) for t in (1, 2, 4, 8, 16, 32)]
+    out = [(f"tile{t}", {"tile": t}, False) for t in (64, 128, 192, 256, 320, 384, 512, 768)]
+    out.append(("tile192-input-order", {"tile": 192, "input_order": True}, False))
+    out.append(("element-scatter", {}, True))
+    return out
+
+
+def autotune(mesh: Mesh, form: Form, coef: torch.Tensor, ncomp: int | None = None,
+             scatter: str = "atomic", fp32: bool = False, candidates=None, reps: int = 10,
+             cache: str | None = None) -> dict:
+    """fem_autotune over tile sizes, tile order and the per-element path; returns
+    {"label", "pattern" (Pattern kwargs), "element_scatter", "ms", "timings", "key"}.
+    cache (or the FEM_AUTOTUNE_CACHE environment variable): a JSON file of earlier
+    choices; a hit is returned without timing."""
+    _need(coef, torch.float64, "coef")
+    ncomp = form.ncomp if ncomp is None else int(ncomp)
+    key = _tune_key(mesh, form, scatter, fp32)
+    path = cache or os.environ.get("FEM_AUTOTUNE_CACHE")
+    table = {}
+    if path and os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+        if key in table:
+            return dict(table[key], key=key, cached=True)
+    cands = list(candidates) if candidates is not None else _default_candidates(mesh)
+    n = len(cands)
+    bflags = (ctypes.c_uint * n)()
+    xflags = (ctypes.c_uint * n)()
+    for i, (_, kw, es) in enumerate(cands):
+        f = L.INPUT_ORDER if kw.get("input_order") else 0
+        if kw.get("tile") is not None:
+            f |= L.tile_flags(kw["tile"])
+        bflags[i] = f
+        xflags[i] = L.ELEMENT_SCATTER if es else 0
+    ms = (ctypes.c_double * n)()
+    best = ctypes.c_int32(-1)
+    ms_ = mesh.cstruct()
+    fs = form.cstruct()
+    rc = L.lib.fem_autotune(ctypes.byref(ms_), ncomp, ctypes.byref(fs), _ptr(coef),
+                            _flags(scatter, False, False, False, fp32), n, bflags, xflags,
+                            int(reps), ms, ctypes.byref(best), _stream_ptr(mesh.coords.device))
+    L.check(rc, "fem_autotune")
+    label, kw, es = cands[best.value]
+    entry = {"label": label, "pattern": dict(kw), "element_scatter": bool(es),
+             "ms": ms[best.value],
+             "timings": {c[0]: (ms[i] if ms[i] >= 0 else None) for i, c in enumerate(cands)}}
+    if path:
+        table[key] = entry
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return dict(entry, key=key, cached=False)
 
 
 class FemAssemble(torch.autograd.Function):

@@ -1,0 +1,83 @@
+"""GPU tests of the tile-plan autotuner (fem_autotune and its JSON cache): every candidate
+is timed or skipped, the choice is the fastest, a pattern built with the choice assembles
+to the oracle's matrix, and a second call is answered from the cache."""
+
+import json
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+from tests._util import scaled_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+BF = (0.0, 0.0, -1.0)
+
+
+def fem():
+    import paper_1802_03433_amd as F
+
+    return F
+
+
+def _dev(m):
+    F = fem()
+    dev = torch.device("cuda:0")
+    return F.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev), m.order)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def test_p1_choice_and_cache(tmp_path):
+    F = fem()
+    m = meshgen.cube_tet(10, seed=41)
+    d = _dev(m)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=41)
+    kap = torch.from_numpy(kappa).cuda()
+    form = F.Form("helmholtz", "sinprod")
+    cache = str(tmp_path / "tune.json")
+    r = F.autotune(d, form, kap, reps=3, cache=cache)
+    assert not r["cached"] and r["key"].startswith("gfx")
+    t = r["timings"]
+    assert len(t) == 10 and all(v is None or v > 0 for v in t.values())
+    assert r["ms"] == min(v for v in t.values() if v is not None)
+    assert t[r["label"]] == r["ms"]
+    pat = F.Pattern(d, **r["pattern"])
+    v, rhs = F.assemble(pat, d, form, kap, element_scatter=r["element_scatter"])
+    rp, ci = oracle.pattern(4, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
+    assert scaled_close(_np(v), ov, oav, RTOL)[0]
+    assert scaled_close(_np(rhs), orhs, oar, RTOL)[0]
+    table = json.load(open(cache))
+    assert r["key"] in table
+    r2 = F.autotune(d, form, kap, reps=3, cache=cache)
+    assert r2["cached"] and r2["label"] == r["label"]
+
+
+def test_p2_tiles_and_skipped_candidates():
+    F = fem()
+    m = meshgen.cube_tet(3, 2, seed=42)
+    d = _dev(m)
+    coef = torch.from_numpy(meshgen.coefficients(m.n_elems, "elasticity", seed=42)).cuda()
+    form = F.Form("elasticity", "const", load_const=BF)
+    cands = [("tile2", {"tile": 2}, False), ("tile8", {"tile": 8}, False),
+             ("tile128", {"tile": 128}, False)]  # 128 is beyond the P2 plan: skipped
+    r = F.autotune(d, form, coef, candidates=cands, reps=2, scatter="coloured")
+    assert r["timings"]["tile128"] is None
+    assert r["label"] in ("tile2", "tile8")
+    pat = F.Pattern(d, ncomp=3, **r["pattern"])
+    v, rhs = F.assemble(pat, d, form, coef, scatter="coloured")
+    rp, ci = oracle.pattern(10, 3, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p2_elasticity(m, _np(coef)[0], _np(coef)[1], "const",
+                                                        BF, rp, ci)
+    assert scaled_close(_np(v), ov, oav, RTOL)[0]
+    with pytest.raises(F.FemError) as e:
+        F.autotune(d, form, coef, candidates=cands, reps=0)
+    assert e.value.code == -1
