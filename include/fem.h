@@ -117,7 +117,8 @@ extern "C" {
 /* fem_build_pattern: elements per tile of the combined scatter, as log2 in bits 8..11
    (0 = default: 192 P1 tetrahedra, 256 P1 triangles, 8 P2 tetrahedra; P1 accepts
    multiples of 64 from 64 to 1024, P2 1 to 64), or for P1 as a count of 64-element
-   wavefronts (1..15) in bits 12..15, which takes precedence */
+   wavefronts (1..15) in bits 12..15, which takes precedence for P1 and is ignored by P2
+   (so one flag word can carry a P1 and a P2 tile size, e.g. for fem_build_batch) */
 #define FEM_TILE_LOG2(k) (((unsigned)(k) & 0xfu) << 8)
 #define FEM_TILE_WAVES(w) (((unsigned)(w) & 0xfu) << 12)
 /* fem_build_pattern: build the P1 tile plan in the input element order.  By default, when

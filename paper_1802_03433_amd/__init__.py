@@ -19,6 +19,7 @@ from .api import (  # noqa: F401
     assemble_backward_rtc,
     assemble_rtc,
     autotune,
+    autotune_batch,
     fem_assemble,
     paper_ell,
     set_allocator,

@@ -305,7 +305,10 @@ class Batch:
     Mesh k's rows are row_offset[k] .. row_offset[k+1] and its stored entries
     nnz_offset[k] .. nnz_offset[k+1] of the batch's values (int64 offsets)."""
 
-    def __init__(self, meshes: list, ncomp: list | None = None, tile: int | None = None):
+    def __init__(self, meshes: list, ncomp: list | None = None, tile: int | None = None,
+                 tile_p1: int | None = None, tile_p2: int | None = None):
+        """tile: one tile size for every member; tile_p1 / tile_p2: per element family
+        (P1 as 64-element wavefronts, P2 as a power of two), e.g. from autotune_batch."""
         if ncomp is None:
             ncomp = [3 if m.order == 2 else 1 for m in meshes]
         self.meshes = list(meshes)
@@ -316,6 +319,15 @@ class Batch:
         flags = 0
         if tile is not None:
             flags |= L.tile_flags(tile)
+        if tile_p1 is not None:
+            if tile_p1 % 64 or not 64 <= tile_p1 <= 960:
+                raise ValueError("tile_p1 must be a multiple of 64 up to 960")
+            flags |= L.TILE_WAVES(tile_p1 // 64)
+        if tile_p2 is not None:
+            k = int(tile_p2).bit_length() - 1
+            if tile_p2 < 1 or (1 << k) != tile_p2 or tile_p2 > 64:
+                raise ValueError("tile_p2 must be a power of two up to 64")
+            flags |= L.TILE_LOG2(k)
         dev = self.meshes[0].coords.device if n else torch.device("cuda")
         rc = L.lib.fem_build_batch(ms, nc, n, flags, ctypes.byref(self._h), _stream_ptr(dev))
         L.check(rc, "fem_build_batch")
@@ -645,6 +657,25 @@ def autotune(mesh: Mesh, form: Form, coef: torch.Tensor, ncomp: int | None = Non
             json.dump(table, f, indent=1, sort_keys=True)
         os.replace(tmp, path)
     return dict(entry, key=key, cached=False)
+
+
+def autotune_batch(meshes: list, forms: list, coefs: list, scatter: str = "atomic",
+                   reps: int = 5, cache: str | None = None) -> dict:
+    """Tile sizes for a batch, one per element family: autotune() on the family's largest
+    member over that family's tile sizes.  Returns {"tile_p1", "tile_p2"} (None for an
+    absent family) for Batch(meshes, tile_p1=..., tile_p2=...)."""
+    out = {"tile_p1": None, "tile_p2": None}
+    for order, key, sizes in ((1, "tile_p1", (64, 128, 192, 256, 320, 384, 512)),
+                              (2, "tile_p2", (1, 2, 4, 8, 16, 32))):
+        fam = [k for k, m in enumerate(meshes) if m.order == order]
+        if not fam:
+            continue
+        k = max(fam, key=lambda j: meshes[j].n_elems)
+        cands = [(f"tile{t}", {"tile": t}, False) for t in sizes]
+        r = autotune(meshes[k], forms[k], coefs[k], scatter=scatter, candidates=cands,
+                     reps=reps, cache=cache)
+        out[key] = r["pattern"]["tile"]
+    return out
 
 
 class FemAssemble(torch.autograd.Function):

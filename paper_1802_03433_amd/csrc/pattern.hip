@@ -409,7 +409,7 @@ int build_pattern_device(fem_pattern *p, const fem_mesh *m, unsigned flags, hipS
     int tile = (p->order == 2) ? 8 : (p->dim == 3 ? 192 : 256);
     const unsigned tsh = (flags >> 8) & 0xfu, tw = (flags >> 12) & 0xfu;
     if (tsh) tile = 1 << tsh;
-    if (tw) tile = 64 * (int)tw;
+    if (tw && p->order == 1) tile = 64 * (int)tw;  // wavefront counts are P1 tiles
     int rc = FEM_ERR_UNSUPPORTED;
     if (E > 0) {
         LocalityOrder o;

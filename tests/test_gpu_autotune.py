@@ -81,3 +81,23 @@ def test_p2_tiles_and_skipped_candidates():
     with pytest.raises(F.FemError) as e:
         F.autotune(d, form, coef, candidates=cands, reps=0)
     assert e.value.code == -1
+
+
+def test_batch_with_tuned_family_tiles():
+    """autotune_batch picks one tile size per element family; a batch built with them
+    (P1 as wavefront counts, P2 as a power of two, in one flag word) matches the oracle."""
+    from tests.test_gpu_batch import _oracle_forward, _small_batch
+
+    F, hm, dm, forms, coefs = _small_batch(seed=5)
+    tiles = fem().autotune_batch(dm, forms, coefs, reps=2)
+    assert tiles["tile_p1"] in (64, 128, 192, 256, 320, 384, 512)
+    assert tiles["tile_p2"] in (1, 2, 4, 8, 16, 32)
+    b = F.Batch(dm, tile_p1=tiles["tile_p1"], tile_p2=tiles["tile_p2"])
+    v, r = F.assemble_batch(b, dm, forms, coefs, scatter="coloured")
+    vn, rn = _np(v), _np(r)
+    for k, m in enumerate(hm):
+        rp, ci, ov, orhs, oav, oar = _oracle_forward(m, forms[k], _np(coefs[k]))
+        assert scaled_close(b.block(vn, k), ov, oav, RTOL)[0]
+        assert scaled_close(b.block(rn, k, rows=True), orhs, oar, RTOL)[0]
+    with pytest.raises(ValueError):
+        F.Batch(dm, tile_p1=100)
