@@ -61,9 +61,10 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    # hipRTC compiles runtime-generated integrand kernels (rtc.hip)
+    # hipRTC compiles runtime-generated integrand kernels (rtc.hip); roctx marks each
+    # C-ABI call for the profiler
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-           "-L/opt/rocm/lib", "-lhiprtc"]
+           "-L/opt/rocm/lib", "-lhiprtc", "-lrocprofiler-sdk-roctx"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

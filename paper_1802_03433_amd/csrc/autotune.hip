@@ -17,6 +17,7 @@ int fem_autotune(const fem_mesh *mesh, int32_t ncomp, const fem_form *form, cons
                  void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_autotune");
     FEM_TRY(check_mesh(mesh, true));
     if (!form) return fail(FEM_ERR_INVALID_ARG, "form is NULL");
     if (n_candidates <= 0 || !build_flags || !ms || !best)

@@ -165,6 +165,7 @@ int fem_build_batch(const fem_mesh *meshes, const int32_t *ncomp, int64_t n_mesh
                     fem_batch **out, void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_build_batch");
     if (!out) return fail(FEM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (n_meshes < 0 || (n_meshes > 0 && (!meshes || !ncomp)))
@@ -304,6 +305,7 @@ int fem_assemble_batch(fem_batch *b, const fem_mesh *meshes, const fem_form *for
                        void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_assemble_batch");
     FEM_TRY(check_batch_meshes(b, meshes, forms));
     if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_PREC_FP32 |
                   FEM_COLOUR_LAUNCHES))
@@ -353,6 +355,7 @@ int fem_assemble_backward_batch(fem_batch *b, const fem_mesh *meshes, const fem_
                                 double *const *grad_coords, unsigned flags, void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_assemble_backward_batch");
     FEM_TRY(check_batch_meshes(b, meshes, forms));
     if (flags & ~(FEM_SCATTER_COLOURED | FEM_ACCUMULATE | FEM_VALIDATE | FEM_COLOUR_LAUNCHES))
         return fail(FEM_ERR_INVALID_ARG, "unknown or unsupported flag bits for a batched adjoint");

@@ -109,6 +109,7 @@ int fem_build_pattern(const fem_mesh *mesh, int32_t ncomp, unsigned flags, fem_p
                       void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_build_pattern");
     if (!out) return fail(FEM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     FEM_TRY(check_mesh(mesh, false));
@@ -261,6 +262,7 @@ int fem_assemble(const fem_pattern *p, const fem_mesh *mesh, const fem_form *for
                  const double *coef, double *values, double *rhs, unsigned flags, void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_assemble");
     FEM_TRY(check_mesh(mesh, true));
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));
@@ -304,6 +306,7 @@ int fem_assemble_backward(const fem_pattern *p, const fem_mesh *mesh, const fem_
                           double *grad_coef, double *grad_coords, unsigned flags, void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_assemble_backward");
     FEM_TRY(check_mesh(mesh, true));
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_form(p, form));

@@ -9,6 +9,8 @@
 
 #include "fem.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 namespace fem {
 
 // ---------------------------------------------------------------------------------------
@@ -17,6 +19,15 @@ namespace fem {
 void set_error(const std::string &msg);
 const char *last_error();
 void clear_error();
+
+// A roctx range around a C-ABI call: rocprofv3 --marker-trace shows each call's host
+// span beside its kernels (no cost beyond a call when no tool is attached).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 struct Status {
     int code = FEM_OK;

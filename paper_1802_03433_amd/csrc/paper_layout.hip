@@ -222,6 +222,7 @@ int fem_assemble_paper(const fem_pattern *p, const fem_mesh *mesh, const fem_for
                        int32_t max_nz, double *values, double *rhs, unsigned flags, void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_assemble_paper");
     FEM_TRY(check_mesh(mesh, true));
     FEM_TRY(check_same_mesh(p, mesh));
     FEM_TRY(check_scalar_p1(p));

@@ -258,6 +258,7 @@ int fem_rtc_compile(int32_t dim, const char *const *sigma, const char *load, int
                     fem_rtc **out)
 {
     clear_error();
+    TraceRange trace_range("fem_rtc_compile");
     if (!out) return fail(FEM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (dim != 2 && dim != 3) return fail(FEM_ERR_INVALID_ARG, "dim must be 2 or 3");
@@ -311,6 +312,7 @@ int fem_rtc_element_matrices(fem_rtc *r, const fem_mesh *mesh, const double *coe
                              double *elmat, void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_rtc_element_matrices");
     if (!r) return fail(FEM_ERR_INVALID_ARG, "rtc is NULL");
     FEM_TRY(check_mesh(mesh, true));
     if (mesh->order != 1 || mesh->dim != r->dim)
@@ -334,6 +336,7 @@ int fem_assemble_rtc(const fem_pattern *p, const fem_mesh *mesh, fem_rtc *r, con
                      double reaction, double *values, double *rhs, unsigned flags, void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_assemble_rtc");
     if (!r) return fail(FEM_ERR_INVALID_ARG, "rtc is NULL");
     FEM_TRY(check_mesh(mesh, true));
     FEM_TRY(check_same_mesh(p, mesh));
@@ -366,6 +369,7 @@ int fem_assemble_backward_rtc(const fem_pattern *p, const fem_mesh *mesh, fem_rt
                               unsigned flags, void *stream)
 {
     clear_error();
+    TraceRange trace_range("fem_assemble_backward_rtc");
     (void)coef;
     (void)reaction;
     (void)grad_rhs;  // the load does not depend on kappa
