@@ -160,6 +160,10 @@ typedef struct {
     int32_t n_colours;   /* element colours of the coloured scatter */
     int32_t max_row;     /* longest dof-level row */
     int64_t device_bytes; /* device memory held by the handle */
+    int64_t n_tiles;      /* tiles of the combined scatter (0: per-element path only) */
+    int32_t tile;         /* elements per tile (threads per workgroup for P1) */
+    int32_t tile_max_nodes; /* most distinct nodes in one tile */
+    int32_t tile_max_slots; /* most distinct stored entries (P1) or node pairs (P2) in a tile */
 } fem_pattern_info;
 
 /*

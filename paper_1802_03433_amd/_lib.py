@@ -125,6 +125,10 @@ class fem_pattern_info(ctypes.Structure):
         ("n_colours", ctypes.c_int32),
         ("max_row", ctypes.c_int32),
         ("device_bytes", ctypes.c_int64),
+        ("n_tiles", ctypes.c_int64),
+        ("tile", ctypes.c_int32),
+        ("tile_max_nodes", ctypes.c_int32),
+        ("tile_max_slots", ctypes.c_int32),
     ]
 
 

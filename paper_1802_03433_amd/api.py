@@ -212,6 +212,10 @@ class Pattern:
         self.n_colours = int(info.n_colours)
         self.max_row = int(info.max_row)
         self.device_bytes = int(info.device_bytes)
+        self.n_tiles = int(info.n_tiles)
+        self.tile = int(info.tile)
+        self.tile_max_nodes = int(info.tile_max_nodes)
+        self.tile_max_slots = int(info.tile_max_slots)
 
     @property
     def handle(self) -> ctypes.c_void_p:

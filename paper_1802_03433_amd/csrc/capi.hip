@@ -153,6 +153,10 @@ int fem_pattern_query(const fem_pattern *p, fem_pattern_info *info)
     info->n_colours = p->has_tiles ? p->n_tile_colours : p->n_colours;
     info->max_row = p->max_row;
     info->device_bytes = p->device_bytes;
+    info->n_tiles = p->has_tiles ? p->n_tiles : 0;
+    info->tile = p->has_tiles ? p->tile : 0;
+    info->tile_max_nodes = p->has_tiles ? p->tile_max_nodes : 0;
+    info->tile_max_slots = p->has_tiles ? p->tile_max_slots : 0;
     return FEM_OK;
 }
 

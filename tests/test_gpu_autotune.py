@@ -101,3 +101,18 @@ def test_batch_with_tuned_family_tiles():
         assert scaled_close(b.block(rn, k, rows=True), orhs, oar, RTOL)[0]
     with pytest.raises(ValueError):
         F.Batch(dm, tile_p1=100)
+
+
+def test_pattern_reports_its_tile_plan():
+    F = fem()
+    m = meshgen.cube_tet(8, seed=43)
+    d = _dev(m)
+    p = F.Pattern(d)
+    assert p.tile == 192 and p.n_tiles == -(-m.n_elems // 192)
+    assert 0 < p.tile_max_nodes <= 4 * 192 and p.tile_max_slots >= p.tile_max_nodes
+    q = F.Pattern(d, tile=128)
+    assert q.tile == 128 and q.n_tiles == -(-m.n_elems // 128)
+    from tests.test_gpu_p1 import _fan_mesh
+
+    f = F.Pattern(_dev(_fan_mesh()))  # rows beyond the tile plan: per-element path only
+    assert f.n_tiles == 0 and f.tile == 0
