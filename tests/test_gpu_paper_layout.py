@@ -135,3 +135,23 @@ def test_paper_layout_rejects():
     with pytest.raises(F.FemError) as e:  # max_nz below the longest row
         F.assemble_paper(p1, d1, F.Form("helmholtz", "none"), kap, ell=(ln, idx))
     assert e.value.code == -1
+
+
+def test_sparse_layout_full_size():
+    """The paper's design at the benchmark's size (64^3 x 6 tets, sin load, N x MAX_NZ):
+    every stored entry against the oracle."""
+    F = fem()
+    m = meshgen.cube_tet(64, seed=0)
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=0)
+    ell = F.paper_ell(pat)
+    v, r = F.assemble_paper(pat, d, F.Form("helmholtz", "sinprod"),
+                            torch.from_numpy(kappa).cuda(), ell=ell)
+    rp, ci = oracle.pattern(4, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
+    ln = _np(ell[0])
+    vals = _np(v)
+    mask = np.arange(vals.shape[1])[None, :] < ln[:, None]
+    _close(vals[mask], ov, oav, "values")
+    _close(_np(r), orhs, oar, "rhs")

@@ -220,3 +220,19 @@ def test_compiled_form_coefficient_adjoint():
                                             ctypes.c_void_p(gk.data_ptr()),
                                             ctypes.c_void_p(d.coords.data_ptr()), 0, None)
     assert rc == -2  # no coordinate gradient for compiled expressions
+
+
+def test_compiled_sin_form_full_size():
+    """The benchmark's compiled form (64^3 x 6 tets, sin-product load written as an
+    expression, atomic scatter): every entry against the oracle."""
+    F = fem()
+    m = meshgen.cube_tet(64, seed=0)
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=0)
+    cf = F.CompiledForm(3, load="sin(pi*x)*sin(pi*y)*sin(pi*z)", degree=2)
+    v, r = F.assemble_rtc(pat, d, cf, torch.from_numpy(kappa).cuda(), reaction=1.0)
+    rp, ci = oracle.pattern(4, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
+    _close(_np(v), ov, oav, "values")
+    _close(_np(r), orhs, oar, "rhs")

@@ -256,3 +256,17 @@ def test_elasticity_rejects_quadratic_load():
     with pytest.raises(F.FemError) as e:
         F.assemble(pat, d, F.Form("elasticity", "poly2", load_poly=(1.0,)), coef)
     assert e.value.code == -2
+
+
+def test_paper_example_full_size():
+    """The Sec. 4.2 example at the benchmark's size and launch configuration (1024^2 x 2
+    triangles, atomic tile scatter): every entry against the oracle."""
+    F = fem()
+    m = meshgen.square_tri(1024, seed=0)
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kap = torch.ones((1, m.n_elems), dtype=torch.float64, device="cuda")
+    v, r = F.assemble(pat, d, F.Form.paper_example(), kap)
+    ov, orhs, oav, oar = _oracle_fwd(m, np.ones(m.n_elems), PAPER_SIGMA, PAPER_F, 1.0)
+    _close(_np(v), ov, oav, "values")
+    _close(_np(r), orhs, oar, "rhs")
