@@ -351,7 +351,7 @@ def _bench_paper_2d(torch, fem, meshgen, dev, steps, n=1024):
     return out
 
 
-def _bench_batch(torch, fem, meshgen, dev, steps, nmin=6, nmax=32):
+def _bench_batch(torch, fem, meshgen, dev, steps, nmin=6, nmax=32, tune=False):
     """512 meshes, n ~ U{nmin..nmax}, 6 n^3 tets each, half P1 Helmholtz (kappa, sin load),
     half P2 elasticity (lambda, mu, body force): one block-diagonal system.  With small
     meshes (n <= 12) launch overhead dominates the per-mesh loop."""
@@ -445,6 +445,19 @@ def _bench_batch(torch, fem, meshgen, dev, steps, nmin=6, nmax=32):
     for p in pats:
         p.close()
     b.close()
+    if tune:
+        # one tile size per element family from the autotuner, then the same batched calls
+        t0 = time.perf_counter()
+        tiles = fem.autotune_batch(meshes, forms, coefs, reps=3)
+        tune_s = time.perf_counter() - t0
+        bt = fem.Batch(meshes, **tiles)
+        res = {"tiles": tiles, "tune_s": tune_s}
+        for sc in ("atomic", "coloured"):
+            fn = lambda sc=sc: fem.assemble_batch(bt, meshes, forms, coefs, values, rhs, scatter=sc)
+            fn()
+            res[f"fwd_{sc}_graph_ms"] = _time_calls(torch, graphed(fn), reps)
+        out["tuned_tiles"] = res
+        bt.close()
     return out
 
 
@@ -631,7 +644,7 @@ def main():
         extra["p2_elasticity"] = _bench_p2(torch, fem, meshgen, dev, max(5, args.steps // 3))
         torch.cuda.empty_cache()
     if not args.no_extra and "batch" in sections and not args.no_batch:
-        extra["batch_512"] = _bench_batch(torch, fem, meshgen, dev, args.steps)
+        extra["batch_512"] = _bench_batch(torch, fem, meshgen, dev, args.steps, tune=True)
         torch.cuda.empty_cache()
         extra["batch_512_small"] = _bench_batch(torch, fem, meshgen, dev, args.steps, 6, 12)
         torch.cuda.empty_cache()
