@@ -114,3 +114,25 @@ def test_runtime_compiled_form_on_the_host():
         fem.CompiledForm(4)
     with pytest.raises(ValueError):
         fem.CompiledForm(2, sigma=[["1"]])
+
+
+def test_new_entry_points_reject_null_arguments(L):
+    """The paper-design, runtime-compilation and autotuning calls check their arguments on
+    the host before any device work."""
+    lib = L.lib
+    assert lib.fem_paper_ell(None, 7, None, None, None) == -1
+    m = L.fem_mesh()
+    f = L.fem_form()
+    assert lib.fem_assemble_paper(None, None, None, None, None, None, 0, None, None, 0, None) == -1
+    assert lib.fem_rtc_element_matrices(None, ctypes.byref(m), None, 1.0, None, None) == -1
+    assert lib.fem_assemble_rtc(None, ctypes.byref(m), None, None, 1.0, None, None, 0, None) == -1
+    assert lib.fem_assemble_backward_rtc(None, ctypes.byref(m), None, None, 1.0, None, None,
+                                         None, None, 0, None) == -1
+    assert lib.fem_rtc_source(None, None, 0) == -1
+    lib.fem_rtc_destroy(None)  # no-op
+    best = ctypes.c_int32(0)
+    assert lib.fem_autotune(None, 1, ctypes.byref(f), None, 0, 1, None, None, 1, None,
+                            ctypes.byref(best), None) == -1
+    out = ctypes.c_void_p()
+    assert lib.fem_rtc_compile(3, None, None, 9, ctypes.byref(out)) == -1  # degree > 5
+    assert not out
