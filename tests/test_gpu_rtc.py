@@ -236,3 +236,36 @@ def test_compiled_sin_form_full_size():
     ov, orhs, oav, oar = oracle.assemble_p1(m, kappa[0], 1.0, "sinprod", None, rp, ci)
     _close(_np(v), ov, oav, "values")
     _close(_np(r), orhs, oar, "rhs")
+
+
+def test_compiled_form_edge_cases():
+    """Accumulate mode; a mesh whose rows are too long for the tile plan (the compiled
+    form's element matrices then go through the per-element path, coloured and atomic);
+    an empty mesh."""
+    from tests.test_gpu_p1 import _fan_mesh
+
+    F = fem()
+    cf = F.CompiledForm(2, sigma=[["1", "-x-y"], ["x+y", "1"]], load="-2*(x*x+y*y)+36",
+                        degree=3)
+    m = _fan_mesh()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    assert pat.n_tiles == 0
+    kap = torch.ones((1, m.n_elems), dtype=torch.float64, device="cuda")
+    rp, ci = oracle.pattern(3, 1, m.n_nodes, m.conn)
+    ov, orhs, oav, oar = oracle.assemble_p1(m, np.ones(m.n_elems), 1.0, "poly2", None, rp, ci,
+                                            sigma=PAPER_SIGMA, poly=PAPER_F)
+    for sc in ("atomic", "coloured"):
+        v, r = F.assemble_rtc(pat, d, cf, kap, reaction=1.0, scatter=sc)
+        _close(_np(v), ov, oav, ("values", sc))
+        _close(_np(r), orhs, oar, ("rhs", sc))
+        F.assemble_rtc(pat, d, cf, kap, reaction=1.0, values=v, rhs=r, scatter=sc,
+                       accumulate=True)
+        _close(_np(v), 2 * ov, 2 * oav, ("accumulated", sc))
+        _close(_np(r), 2 * orhs, 2 * oar, ("accumulated rhs", sc))
+    # empty mesh: nothing to assemble, outputs cleared
+    e = F.Mesh(torch.zeros((2, 3), dtype=torch.float64, device="cuda"),
+               torch.zeros((3, 0), dtype=torch.int32, device="cuda"))
+    pe = F.Pattern(e)
+    v, r = F.assemble_rtc(pe, e, cf, torch.zeros((1, 0), dtype=torch.float64, device="cuda"))
+    assert v.numel() == pe.nnz and (_np(r) == 0).all()

@@ -270,3 +270,27 @@ def test_paper_example_full_size():
     ov, orhs, oav, oar = _oracle_fwd(m, np.ones(m.n_elems), PAPER_SIGMA, PAPER_F, 1.0)
     _close(_np(v), ov, oav, "values")
     _close(_np(r), orhs, oar, "rhs")
+
+
+def test_sigma_form_accumulate_and_validate():
+    F = fem()
+    m, sig, poly, c = CASES["random_tri7"]()
+    d = _dev(m)
+    pat = F.Pattern(d)
+    kappa = meshgen.coefficients(m.n_elems, "helmholtz", seed=12)
+    kap = torch.from_numpy(kappa).cuda()
+    form = _form(F, sig, poly, c)
+    v, r = F.assemble(pat, d, form, kap, validate=True)
+    F.assemble(pat, d, form, kap, values=v, rhs=r, accumulate=True, scatter="two-pass")
+    ov, orhs, oav, oar = _oracle_fwd(m, kappa[0], sig, poly, c)
+    _close(_np(v), 2 * ov, 2 * oav, "values")
+    _close(_np(r), 2 * orhs, 2 * oar, "rhs")
+    # a zero-area element is reported under validation
+    bad = meshgen.Mesh(m.dim, m.order, m.n, m.coords.copy(), m.conn.copy())
+    k = bad.conn[:, 0]
+    bad.coords[:, k[2]] = bad.coords[:, k[0]]  # two coincident vertices: det J = 0 exactly
+    db = _dev(bad)
+    pb = F.Pattern(db)
+    with pytest.raises(F.FemError) as e:
+        F.assemble(pb, db, form, kap, validate=True)
+    assert e.value.code == -5
