@@ -294,3 +294,32 @@ def test_sigma_form_accumulate_and_validate():
     with pytest.raises(F.FemError) as e:
         F.assemble(pb, db, form, kap, validate=True)
     assert e.value.code == -5
+
+
+def test_batch_adjoint_of_sigma_meshes():
+    """The batched adjoint of the matrix-coefficient form: each member bit-identical to its
+    single-mesh adjoint (coloured), and against the oracle."""
+    F = fem()
+    dev = torch.device("cuda:0")
+    hm = [meshgen.square_tri(n, seed=50 + n) for n in (4, 7, 3)]
+    dm = [F.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev), 1)
+          for m in hm]
+    sigs = [_random_sigma(2, 60 + k) for k in range(3)]
+    cs = [1.0 + 0.2 * k for k in range(3)]
+    forms = [_form(F, s, p, c) for (s, p), c in zip(sigs, cs)]
+    coefs = [torch.from_numpy(meshgen.coefficients(m.n_elems, "helmholtz", seed=70 + k)).to(dev)
+             for k, m in enumerate(hm)]
+    b = F.Batch(dm)
+    G, g = (torch.from_numpy(t).to(dev) for t in meshgen.upstream_grads(b.nnz, b.n_rows, seed=71))
+    gks, gxs = F.assemble_backward_batch(b, dm, forms, coefs, G, g, scatter="coloured")
+    for k, m in enumerate(hm):
+        pk = F.Pattern(dm[k])
+        Gk, gk_ = b.block(G, k).contiguous(), b.block(g, k, rows=True).contiguous()
+        gk1, gx1 = F.assemble_backward(pk, dm[k], forms[k], coefs[k], Gk, gk_, scatter="coloured")
+        assert np.array_equal(_np(gks[k]), _np(gk1)) and np.array_equal(_np(gxs[k]), _np(gx1))
+        s, p = sigs[k]
+        rp, ci = oracle.pattern(3, 1, m.n_nodes, m.conn)
+        dk, adk, dx, adx = oracle.backward_p1(m, _np(coefs[k])[0], cs[k], "poly2", [0.7], rp, ci,
+                                              _np(Gk), _np(gk_), sigma=s, poly=p)
+        _close(_np(gks[k])[0], dk, adk, "dkappa")
+        _close(_np(gxs[k]), dx, adx, "dcoords")
