@@ -170,15 +170,23 @@ std::string make_source(int D, const char *const *sigma, const char *load, int d
         }
         s += "};\n";
     }
-    s += R"(#pragma unroll
+    s += R"(        double C[NP][D];  // C = B S
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int bb = 0; bb < D; ++bb) {
+                double t = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) t += B[i][a] * S[a][bb];
+                C[i][bb] = t;
+            }
+#pragma unroll
         for (int i = 0; i < NP; ++i)
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
                 double g = 0.0;
 #pragma unroll
-                for (int a = 0; a < D; ++a)
-#pragma unroll
-                    for (int bb = 0; bb < D; ++bb) g += B[i][a] * S[a][bb] * B[j][bb];
+                for (int bb = 0; bb < D; ++bb) g += C[i][bb] * B[j][bb];
                 A[i][j] += wv * (kap * g + c * RL[q][i] * RL[q][j]);
             }
 )";
